@@ -1,0 +1,126 @@
+"""Pins for the solvers: IHS closed form with lambda = 0, V = C reduction to
+plain FISTA, the fixed point of an outer iteration, and the power iteration
+against the full-mask closed form."""
+import numpy as np
+
+import synth
+from oracle import cartesian as cart
+from oracle import recon
+from oracle import sketch as sk
+
+
+def _rand(shape, seed):
+    g = np.random.default_rng(seed)
+    return g.standard_normal(shape) + 1j * g.standard_normal(shape)
+
+
+def _small(seed=0, n=16, C=6):
+    shape = (n, n)
+    x = synth.phantom(shape, seed + 1)
+    maps = synth.coil_maps(shape, C, seed + 2)
+    mask = synth.mask_1d_vd(n, n, seed + 3, n_center=4, accel=2)
+    y = cart.forward(x, maps, mask) + 1e-3 * _rand(shape + (C,), seed + 4) * mask[..., None]
+    return shape, x, maps, mask, y.reshape(-1, C)
+
+
+def _nfn(mask):
+    return lambda v, m: cart.normal(v, m, mask)
+
+
+def _dense_normal(maps, mask):
+    A = cart.dense_matrix(maps, mask)
+    return A.conj().T @ A
+
+
+def test_subproblem_lambda0_reaches_closed_form():
+    # Eq. 10 with g = 0: x^{t+1} = x^t - N_S^{-1} d  (dense solve, tiny case).
+    # Random (non-smooth) maps keep the sketched Hessian well conditioned.
+    shape = (16, 16)
+    C = 5
+    maps = _rand(shape + (C,), 21)
+    mask = synth.mask_1d_vd(16, 16, 4, n_center=4, accel=2)
+    y = cart.forward(synth.phantom(shape, 1), maps, mask).reshape(-1, C)
+    st = recon.SketchState(maps, y, None)
+    ms = st.maps_for(2, 2, 7, 1)
+    NS = _dense_normal(ms, mask)
+    ev = np.linalg.eigvalsh(NS)
+    assert ev.min() > 1e-3 * ev.max()
+    xt = _rand(shape, 9)
+    b = cart.adjoint(y.reshape(shape + (-1,)), maps, mask)
+    d = cart.normal(xt, maps, mask) - b
+    sol = xt.reshape(-1) - np.linalg.solve(NS, d.reshape(-1))
+    got = recon.sketched_subproblem(lambda v: cart.normal(v, ms, mask), d, xt,
+                                    1.0 / ev.max(), 0.0, 2000)
+    assert np.linalg.norm(got.reshape(-1) - sol) < 1e-8 * np.linalg.norm(sol)
+
+
+def test_ihs_outer_error_contracts_lambda0():
+    # IHS converges geometrically in t (Sec. 2.2.2).  lambda = 0, smooth maps
+    # with PCA high-energy coils; the error is measured on the well-conditioned
+    # eigenspace of N (eigenvalues above 1% of the largest).
+    shape = (16, 16)
+    C = 6
+    maps = synth.coil_maps(shape, C, 3)
+    mask = synth.mask_1d_vd(16, 16, 5, n_center=4, accel=2)
+    y = cart.forward(synth.phantom(shape, 2), maps, mask).reshape(-1, C)
+    b = cart.adjoint(y.reshape(shape + (-1,)), maps, mask)
+    w, Q = np.linalg.eigh(_dense_normal(maps, mask))
+    keep = w > 1e-2 * w.max()
+    Qk = Q[:, keep]
+    xls = Qk @ ((Qk.conj().T @ b.reshape(-1)) / w[keep])
+    errs = []
+
+    def cb(t, xt):
+        errs.append(np.linalg.norm(Qk.conj().T @ (xt.reshape(-1) - xls)))
+    recon.coil_sketch(_nfn(mask), maps, y, None, b, np.zeros(shape, complex),
+                      V=3, S=2, seed=3, T=7, K=200, lam=0.0, callback=cb)
+    assert all(errs[i + 1] < errs[i] for i in range(6))
+    assert errs[6] < 1e-2 * errs[0]
+
+
+def test_v_equals_c_matches_plain_fista():
+    shape, x, maps, mask, y = _small(C=5)
+    C = 5
+    b = cart.adjoint(y.reshape(shape + (-1,)), maps, mask)
+    x0 = np.zeros(shape, complex)
+    alpha, lam, K = 0.9, 1e-2, 7
+    xs, _, st = recon.coil_sketch(_nfn(mask), maps, y, None, b, x0, V=C, S=0, seed=1,
+                                  T=1, K=K, lam=lam, alpha=alpha)
+    xf = recon.fista_full(lambda v: cart.normal(v, maps, mask), b, x0, alpha, lam, K)
+    assert np.max(np.abs(xs - xf)) < 1e-12
+
+
+def test_fixed_point_of_outer_iteration():
+    shape, x, maps, mask, y = _small(C=6)
+    b = cart.adjoint(y.reshape(shape + (-1,)), maps, mask)
+    lam = 5e-3
+    xinf = recon.fista_full(lambda v: cart.normal(v, maps, mask), b,
+                            np.zeros(shape, complex), 1.0, lam, 3000)
+    st = recon.SketchState(maps, y, None)
+    for t in (1, 2):
+        ms = st.maps_for(3, 2, 11, t)
+        d = cart.normal(xinf, maps, mask) - b
+        L = recon.power_iteration(lambda v: cart.normal(v, ms, mask), shape)
+        x1 = recon.sketched_subproblem(lambda v: cart.normal(v, ms, mask), d, xinf,
+                                       1.0 / L, lam, 10)
+        assert np.linalg.norm(x1 - xinf) < 1e-6 * np.linalg.norm(xinf)
+
+
+def test_power_iteration_full_mask_closed_form():
+    shape = (16, 16)
+    maps = _rand(shape + (3,), 5)
+    ones = np.ones(shape, np.uint8)
+    L = recon.power_iteration(lambda v: cart.normal(v, maps, ones), shape, 200)
+    exact = np.max(np.sum(np.abs(maps) ** 2, axis=-1))
+    assert abs(L - exact) < 1e-3 * exact
+
+
+def test_objective_decreases_and_nrmse():
+    shape, x, maps, mask, y = _small(C=6)
+    b = cart.adjoint(y.reshape(shape + (-1,)), maps, mask)
+    fwd = lambda v: cart.forward(v, maps, mask).reshape(-1, 6)
+    objs = []
+    recon.fista_full(lambda v: cart.normal(v, maps, mask), b, np.zeros(shape, complex),
+                     1.0, 1e-3, 30, callback=lambda i, xi: objs.append(recon.objective(xi, fwd, y, 1e-3)))
+    assert objs[-1] < objs[0]
+    assert recon.nrmse(x, x) == 0.0

@@ -1,0 +1,111 @@
+"""Pins for PCA virtual coils and the structured sketch (Sec. 2.3.2-2.3.3)."""
+import itertools
+import os
+
+import numpy as np
+
+import synth
+from oracle import cartesian as cart
+from oracle import nufft
+from oracle import sketch as sk
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rand(shape, seed):
+    g = np.random.default_rng(seed)
+    return g.standard_normal(shape) + 1j * g.standard_normal(shape)
+
+
+def test_splitmix64_reference_outputs():
+    vals = [int(l, 16) for l in open(os.path.join(GOLD, "splitmix64_seed0.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert [sk.splitmix64_output(0, n) for n in (1, 2, 3)] == vals
+
+
+def test_rademacher_signs_balanced_and_fresh_per_iteration():
+    r = [sk.rademacher(12345, t, 6, 26) for t in range(1, 41)]
+    allv = np.concatenate([a.ravel() for a in r])
+    assert set(np.unique(allv)) == {-1, 1}
+    assert abs(allv.mean()) < 0.05
+    assert not np.array_equal(r[0], r[1])
+    assert np.array_equal(r[3], sk.rademacher(12345, 4, 6, 26))
+
+
+def _problem(seed=0, C=6, n=24):
+    shape = (n, n)
+    x = synth.phantom(shape, seed + 1)
+    maps = synth.coil_maps(shape, C, seed + 2)
+    mask = synth.mask_1d_vd(n, n, seed + 3, n_center=6, accel=2)
+    y = cart.forward(x, maps, mask).reshape(-1, C)
+    return shape, x, maps, mask, y
+
+
+def test_pca_properties():
+    shape, x, maps, mask, y = _problem()
+    R = sk.covariance(y)
+    lam, U = sk.pca(R)
+    nR = np.linalg.norm(R)
+    assert np.linalg.norm(R @ U - U * lam[None, :]) < 1e-12 * nR
+    assert np.linalg.norm(U.conj().T @ U - np.eye(U.shape[0])) < 1e-12
+    assert np.all(np.diff(lam) <= 0)
+    assert abs(lam.sum() - np.sum(np.abs(y) ** 2)) < 1e-10 * lam.sum()
+    kv = sk.virtual_data(y, U)
+    G = kv.conj().T @ kv   # virtual channels orthogonal, energies = lambda
+    assert np.linalg.norm(G - np.diag(lam)) < 1e-10 * lam.sum()
+    for j in range(U.shape[1]):
+        i = int(np.argmax(np.abs(U[:, j])))
+        assert abs(U[i, j].imag) < 1e-14 and U[i, j].real > 0
+
+
+def test_rotation_invariance_cartesian_and_nufft():
+    shape, x, maps, mask, y = _problem(5)
+    lam, U = sk.pca(sk.covariance(y))
+    vm = sk.virtual_maps(maps, U)
+    z = _rand(shape, 1)
+    a = cart.normal(z, maps, mask)
+    b = cart.normal(z, vm, mask)
+    assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(a))
+    coords = synth.radial_traj(24, 6)
+    plan = nufft.Plan(shape, coords, synth.radial_dcf(coords, 24))
+    a = plan.normal(z, maps)
+    b = plan.normal(z, vm)
+    assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(a))
+
+
+def test_v_equals_c_reduces_exactly():
+    shape, x, maps, mask, y = _problem(7)
+    C = maps.shape[-1]
+    lam, U = sk.pca(sk.covariance(y))
+    vm = sk.virtual_maps(maps, U)
+    sm, _ = sk.sketch_for_iteration(vm, C, 0, 99, 1)
+    z = _rand(shape, 2)
+    a = cart.normal(z, maps, mask)
+    b = cart.normal(z, sm, mask)
+    assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(a))
+
+
+def test_exact_expectation_over_all_sign_patterns():
+    # E over every Rademacher pattern of N_S equals N (E[S~^T S~] = I)
+    shape, x, maps, mask, y = _problem(9, C=5, n=16)
+    C, V, S = 5, 2, 2
+    lam, U = sk.pca(sk.covariance(y))
+    vm = sk.virtual_maps(maps, U)
+    z = _rand(shape, 3)
+    ref = cart.normal(z, maps, mask)
+    acc = np.zeros_like(ref)
+    pats = list(itertools.product([-1, 1], repeat=S * (C - V)))
+    for p in pats:
+        St = sk.sketch_matrix(V, S, C, np.array(p).reshape(S, C - V))
+        acc += cart.normal(z, sk.sketched_maps(vm, St), mask)
+    acc /= len(pats)
+    assert np.max(np.abs(acc - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_sketch_matrix_structure():
+    s = sk.rademacher(1, 1, 3, 5)
+    St = sk.sketch_matrix(2, 3, 7, s)
+    assert St.shape == (5, 7)
+    assert np.array_equal(St[:2, :2], np.eye(2))
+    assert np.all(St[:2, 2:] == 0) and np.all(St[2:, :2] == 0)
+    assert np.allclose(np.abs(St[2:, 2:]), 1 / np.sqrt(3))
