@@ -1,0 +1,207 @@
+/*
+ * coilsketch.h -- C ABI of the MI355X (gfx950) coil-sketching library.
+ *
+ * The library applies the multi-coil SENSE operator of Oscanoa et al.,
+ * "Coil Sketching for computationally-efficient MR iterative reconstruction"
+ * (Sec. 2.1, Eqs. 1-2 and 5), its adjoint and normal operator, builds the
+ * structured coil sketch of Sec. 2.3.2-2.3.3 (Eqs. 11-13), and runs the
+ * reconstruction of Algorithm 1 (Sec. 2.3.4) with FISTA inner solves and the
+ * l1-wavelet regularizer of Sec. 2.1.1.  Every step runs in HIP kernels.
+ *
+ * General rules
+ *  - Every array argument marked "device" is a device pointer owned by the
+ *    caller; it must stay valid until the call's work on the context stream
+ *    has finished.  Host pointers are marked "host".
+ *  - Complex data is complex64: interleaved (re, im) float32.
+ *  - Images are row-major with the last axis fastest: [nz][ny][nx] (3D) or
+ *    [ny][nx] (2D).  For the non-Cartesian operator the image index i along
+ *    an axis of length n has the centred coordinate i - n/2.
+ *  - Coil stacks are pixel-major with the coil index fastest: maps [D][C],
+ *    data [N][C].  Cartesian data is zero-filled on the full grid (N = D),
+ *    in the non-centred FFT layout (DC at index 0).
+ *  - Non-Cartesian coordinates are float32 [N][ndim] in cycles/FOV, column 0
+ *    the x (fastest image axis) frequency, each within [-n_a/2, n_a/2).
+ *  - All calls are asynchronous on the context's stream unless stated.
+ *  - Return codes: CS_OK (0), CS_EINVAL (-1: null pointer, bad size, V+S > C,
+ *    unsupported FFT length), CS_EUNSUPPORTED (-2), CS_EHIP (-3: a HIP runtime
+ *    error), CS_ENUMERIC (-4: NaN or divergence).  cs_last_error() gives a
+ *    message.  No exception crosses the ABI.
+ *  - A context is bound to one stream and is not thread-safe.  It allocates
+ *    its working memory in cs_create()/cs_set_operator() and frees it in
+ *    cs_destroy(); operator calls allocate nothing.
+ */
+#ifndef COILSKETCH_H
+#define COILSKETCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cs_ctx cs_ctx;
+
+enum {
+  CS_OK = 0,
+  CS_EINVAL = -1,
+  CS_EUNSUPPORTED = -2,
+  CS_EHIP = -3,
+  CS_ENUMERIC = -4
+};
+
+enum { CS_CART = 0, CS_NONCART = 1 };
+
+/* Geometry of one operator (Sec. 2.1: image x in C^D, C channels, N samples). */
+typedef struct {
+  int ndim;          /* 2 or 3 */
+  int n[3];          /* image size per axis, slowest first: {nz, ny, nx} or {ny, nx, 0} */
+  int ncoil;         /* C: coils of the full operator */
+  int kind;          /* CS_CART (F~ = U F~_u) or CS_NONCART (F~ = F~_n, NUFFT) */
+  long long nsamp;   /* N: samples per coil (non-Cartesian); ignored for Cartesian */
+  float sigma;       /* NUFFT grid oversampling (e.g. 1.25); m_a = round(sigma n_a) */
+  int kwidth;        /* Kaiser-Bessel width in grid cells; only 4 is supported */
+  float beta;        /* KB shape; 0 selects Beatty's formula */
+  int wav_levels;    /* levels of the db4 transform (image sizes divisible by 2^levels) */
+} cs_geom;
+
+/* Create a context for geometry g on HIP stream `stream` (a hipStream_t, or
+ * NULL for the default stream).  On success *out holds the context. */
+int cs_create(const cs_geom* g, void* stream, cs_ctx** out);
+
+/* Destroy a context and free its device memory (synchronises its stream). */
+void cs_destroy(cs_ctx* ctx);
+
+/* Message for the last error on ctx (or the last failed cs_create if ctx is
+ * NULL).  The string is owned by the library. */
+const char* cs_last_error(const cs_ctx* ctx);
+
+/* Bind the full-coil operator.  maps: device [D][C] complex64, borrowed (must
+ * outlive the context's use of it).  Cartesian: mask device uint8 [D]
+ * (non-centred), coords/dcf NULL.  Non-Cartesian: coords device float32
+ * [N][ndim], dcf device float32 [N] (may be NULL for w = 1), mask NULL; the
+ * coordinates are copied, binned and sorted here (synchronous).  Sec. 2.1:
+ * A = W^1/2 F C, y = W^1/2 k. */
+int cs_set_operator(cs_ctx* ctx, const void* maps, const uint8_t* mask,
+                    const float* coords, const float* dcf);
+
+/* y = W^1/2 F (c_c * x) for the ncoil maps given (Eq. 5).  maps device
+ * [D][ncoil], x device [D], y device [N][ncoil] (overwritten; samples in the
+ * caller's order). */
+int sense_apply(cs_ctx* ctx, const void* maps, int ncoil, const void* x, void* y);
+
+/* x = sum_c conj(c_c) * F^H W^1/2 y_c, the adjoint of sense_apply.  y device
+ * [N][ncoil], x device [D] (overwritten). */
+int sense_adjoint(cs_ctx* ctx, const void* maps, int ncoil, const void* y, void* x);
+
+/* out = sum_c conj(c_c) * F^H W F (c_c * x) = A^H A x for the ncoil maps
+ * given: the full set (A) or a sketched set (A_S^t, Eq. 12).  x, out device
+ * [D]; they must not alias. */
+int normal_apply(cs_ctx* ctx, const void* maps, int ncoil, const void* x, void* out);
+
+/* Structured sketch of Sec. 2.3.2-2.3.3.  On the first call after
+ * cs_set_operator (or when `refresh` is non-zero) the coil covariance
+ * R = sum_i k_i k_i^H of the raw samples k_i = y_i / sqrt(w_i) is accumulated
+ * in FP64, R = U diag(lambda) U^H is found by a FP64 Jacobi eigensolver
+ * (lambda descending; each eigenvector's largest-magnitude entry made real
+ * positive), and the virtual maps c' = U^H c are formed and cached.  Each call
+ * then draws the Rademacher block S~_S^t in {+1,-1}^{S x (C-V)} from
+ * SplitMix64(seed) at counter (t << 32 | a (C-V) + b) + 1 (sign = top bit) and
+ * writes the V + S sketched maps c^ = [c'_1..V ; (S~_S^t / sqrt(S)) c'_V+1..C].
+ *   y       device [N][C] data (used for the covariance only)
+ *   smaps   device [D][V+S] output
+ *   eig     host [C] float64 (may be NULL): lambda
+ *   U_out   host [C][C] complex128 row-major, column j = eigenvector j (may be NULL)
+ *   signs   host [S][C-V] int8 (may be NULL): the draw.  Synchronises when any
+ *           host output is requested.
+ * Requires V >= 0, S >= 0, 0 < V + S <= C, and S > 0 or V = C. */
+int sketch_build(cs_ctx* ctx, const void* y, int V, int S, uint64_t seed, int t,
+                 int refresh, void* smaps, double* eig, double* U_out,
+                 int8_t* signs);
+
+/* Recon modes */
+enum { CS_RECON_FULL = 0, CS_RECON_SKETCH = 1 };
+
+typedef struct {
+  int mode;          /* CS_RECON_FULL: plain FISTA; CS_RECON_SKETCH: Algorithm 1 */
+  float lam;         /* l1-wavelet weight lambda */
+  int T;             /* FULL: FISTA iterations; SKETCH: outer iterations */
+  int K;             /* SKETCH: inner FISTA iterations per subproblem */
+  int V, S;          /* sketch design (Sec. 2.3.3) */
+  uint64_t seed;     /* sketch seed */
+  int t0;            /* first outer index (resume: x_inout holds x^{t0}) */
+  double step;       /* FISTA step alpha; <= 0 selects 1/L from the power
+                        iteration on the first subproblem (Sec. 3.3.1) */
+  int n_pow;         /* power-iteration count (default 30) */
+  int reuse_b;       /* non-zero: reuse b = A^H y from the previous call */
+  const void* x_ref; /* device [D] or NULL: per-iteration distance reference */
+} cs_recon_params;
+
+typedef struct {
+  /* host arrays of length >= T, filled when non-NULL */
+  double* dist;      /* ||x^t - x_ref|| / ||x_ref|| (FP64) after each iteration */
+  double* time_ms;   /* GPU time since the start of the loop, per iteration */
+  /* scalar outputs */
+  double alpha;      /* step used */
+  long long n_full_applies;    /* full-coil normal applies */
+  long long n_sketch_applies;  /* sketched normal applies */
+  long long n_prox;            /* wavelet prox evaluations */
+  double total_ms;   /* GPU time of the whole call */
+  /* GPU time (HIP events on the context stream) spent in each phase of the
+   * iterations: full-coil normal applies, sketched normal applies, wavelet
+   * prox, and forming the sketched maps */
+  double ms_full_normal, ms_sketch_normal, ms_prox, ms_sketch;
+} cs_recon_stats;
+
+/* Reconstruction (Algorithm 1 or plain FISTA) of x from data y on the
+ * operator bound by cs_set_operator.  y device [N][C]; x_inout device [D]:
+ * x^{t0} on entry, the result on exit.  Synchronous. */
+int recon_run(cs_ctx* ctx, const void* y, const cs_recon_params* p,
+              void* x_inout, cs_recon_stats* st);
+
+/* ---- building blocks exposed for testing and benchmarking ---------------- */
+
+/* Periodized db4 wavelet prox  out = Psi^H soft(Psi v, tau)  (Sec. 2.1,
+ * regularizer 2).  v, out device [D] (may alias). */
+int cs_prox_l1wav(cs_ctx* ctx, const void* v, float tau, void* out);
+
+/* Forward / inverse db4 transform (Mallat layout), out-of-place, device [D]. */
+int cs_dwt(cs_ctx* ctx, const void* x, void* coef);
+int cs_idwt(cs_ctx* ctx, const void* coef, void* x);
+
+/* Coil mixing out[d][j] = sum_c in[d][c] * M[j][c] on MFMA (split-BF16,
+ * FP32 accumulate).  in device [D][cin], out device [D][cout], M host
+ * complex128 [cout][cin] row-major. */
+int cs_coil_mix(cs_ctx* ctx, const void* in, int cin, const double* M, int cout,
+                void* out);
+
+/* FP64 inner product <a, b> = sum conj(a) b of two device complex64 [D]
+ * vectors; result host double[2] (re, im).  Synchronous. */
+int cs_dot(cs_ctx* ctx, const void* a, const void* b, double* out);
+
+/* Power iteration on the normal operator with the given maps (Sec. 3.3.1):
+ * n_iter normalised applies from the normalised all-ones image; returns
+ * L = ||N v_n|| in *L.  Synchronous. */
+int cs_power_iteration(cs_ctx* ctx, const void* maps, int ncoil, int n_iter,
+                       double* L);
+
+/* Grid dimensions of the operator (NUFFT oversampled grid, or the image for
+ * Cartesian), slowest first; m[2] = 1 in 2D. */
+int cs_grid_shape(const cs_ctx* ctx, int m[3]);
+
+/* Per-kernel timing with HIP events recorded on the context stream around
+ * every kernel launch while enabled.  Kernel kinds (index into the arrays):
+ * 0 FFT axis pass, 1 interpolation, 2 spreading, 3 sample gather,
+ * 4 wavelet axis pass, 5 soft threshold, 6 element-wise vector op,
+ * 7 FP64 reduction, 8 covariance, 9 eigensolver, 10 coil mixing.
+ * cs_profile_read synchronises, writes the summed milliseconds and launch
+ * counts per kind (host arrays of length CS_NKERNELS) and resets them. */
+#define CS_NKERNELS 11
+int cs_profile_enable(cs_ctx* ctx, int on);
+int cs_profile_read(cs_ctx* ctx, double* ms, long long* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COILSKETCH_H */

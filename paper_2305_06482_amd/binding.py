@@ -1,0 +1,404 @@
+"""Thin ctypes binding over ``libcoilsketch.so`` (argument marshalling only).
+
+Every call forwards device pointers of caller-owned PyTorch tensors and the
+context's HIP stream to the C ABI declared in ``include/coilsketch.h``; all
+arithmetic runs in the library's HIP kernels.  There is no fallback: if the
+library is missing or a call fails, an exception is raised.
+
+Layouts (see the header): images are complex64 row-major ``(nz, ny, nx)`` or
+``(ny, nx)``; coil stacks are pixel-major with the coil index fastest
+(``maps[..., c]``, data ``[N, C]``); coordinates are float32 ``[N, ndim]`` in
+cycles/FOV with column 0 the x frequency.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcoilsketch.so")
+
+CS_CART = 0
+CS_NONCART = 1
+CS_RECON_FULL = 0
+CS_RECON_SKETCH = 1
+
+EXPORTED = [
+    "cs_create", "cs_destroy", "cs_last_error", "cs_set_operator", "sense_apply",
+    "sense_adjoint", "normal_apply", "sketch_build", "recon_run", "cs_prox_l1wav",
+    "cs_dwt", "cs_idwt", "cs_coil_mix", "cs_dot", "cs_power_iteration", "cs_grid_shape",
+    "cs_profile_enable", "cs_profile_read",
+]
+NKERNELS = 11
+KERNEL_KINDS = ["fft_pass", "interp", "spread", "gather", "wavelet", "soft", "vec", "reduce",
+                "covariance", "eigensolver", "coil_mix"]
+
+
+class CSError(RuntimeError):
+    pass
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int),
+        ("n", ctypes.c_int * 3),
+        ("ncoil", ctypes.c_int),
+        ("kind", ctypes.c_int),
+        ("nsamp", ctypes.c_longlong),
+        ("sigma", ctypes.c_float),
+        ("kwidth", ctypes.c_int),
+        ("beta", ctypes.c_float),
+        ("wav_levels", ctypes.c_int),
+    ]
+
+
+class ReconParams(ctypes.Structure):
+    _fields_ = [
+        ("mode", ctypes.c_int),
+        ("lam", ctypes.c_float),
+        ("T", ctypes.c_int),
+        ("K", ctypes.c_int),
+        ("V", ctypes.c_int),
+        ("S", ctypes.c_int),
+        ("seed", ctypes.c_uint64),
+        ("t0", ctypes.c_int),
+        ("step", ctypes.c_double),
+        ("n_pow", ctypes.c_int),
+        ("reuse_b", ctypes.c_int),
+        ("x_ref", ctypes.c_void_p),
+    ]
+
+
+class ReconStats(ctypes.Structure):
+    _fields_ = [
+        ("dist", ctypes.POINTER(ctypes.c_double)),
+        ("time_ms", ctypes.POINTER(ctypes.c_double)),
+        ("alpha", ctypes.c_double),
+        ("n_full_applies", ctypes.c_longlong),
+        ("n_sketch_applies", ctypes.c_longlong),
+        ("n_prox", ctypes.c_longlong),
+        ("total_ms", ctypes.c_double),
+        ("ms_full_normal", ctypes.c_double),
+        ("ms_sketch_normal", ctypes.c_double),
+        ("ms_prox", ctypes.c_double),
+        ("ms_sketch", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise CSError(f"{LIB_PATH} not found: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, ci, cf, cd = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_double
+    lib.cs_create.argtypes = [ctypes.POINTER(Geom), vp, ctypes.POINTER(vp)]
+    lib.cs_destroy.argtypes = [vp]
+    lib.cs_destroy.restype = None
+    lib.cs_last_error.argtypes = [vp]
+    lib.cs_last_error.restype = ctypes.c_char_p
+    lib.cs_set_operator.argtypes = [vp, vp, vp, vp, vp]
+    for name in ("sense_apply", "sense_adjoint", "normal_apply"):
+        getattr(lib, name).argtypes = [vp, vp, ci, vp, vp]
+    lib.sketch_build.argtypes = [vp, vp, ci, ci, ctypes.c_uint64, ci, ci, vp, vp, vp, vp]
+    lib.recon_run.argtypes = [vp, vp, ctypes.POINTER(ReconParams), vp,
+                              ctypes.POINTER(ReconStats)]
+    lib.cs_prox_l1wav.argtypes = [vp, vp, cf, vp]
+    lib.cs_dwt.argtypes = [vp, vp, vp]
+    lib.cs_idwt.argtypes = [vp, vp, vp]
+    lib.cs_coil_mix.argtypes = [vp, vp, ci, vp, ci, vp]
+    lib.cs_dot.argtypes = [vp, vp, vp, vp]
+    lib.cs_power_iteration.argtypes = [vp, vp, ci, ci, vp]
+    lib.cs_grid_shape.argtypes = [vp, vp]
+    lib.cs_profile_enable.argtypes = [vp, ci]
+    lib.cs_profile_read.argtypes = [vp, vp, vp]
+    for name in EXPORTED:
+        f = getattr(lib, name)
+        if name not in ("cs_destroy", "cs_last_error"):
+            f.restype = ci
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, dtype, shape, name):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+@dataclass
+class ReconResult:
+    x: torch.Tensor
+    alpha: float
+    n_full_applies: int
+    n_sketch_applies: int
+    n_prox: int
+    total_ms: float
+    ms_full_normal: float = 0.0
+    ms_sketch_normal: float = 0.0
+    ms_prox: float = 0.0
+    ms_sketch: float = 0.0
+    time_ms: list = field(default_factory=list)
+    dist: list = field(default_factory=list)
+
+
+class Context:
+    """One operator geometry bound to the current HIP stream."""
+
+    def __init__(self, shape, ncoil, kind="cart", nsamp=0, sigma=1.25, kwidth=4,
+                 beta=0.0, wav_levels=4, device=None):
+        self.lib = load()
+        self.shape = tuple(int(s) for s in shape)
+        self.ndim = len(self.shape)
+        self.C = int(ncoil)
+        self.kind = CS_CART if kind == "cart" else CS_NONCART
+        self.N = int(nsamp) if self.kind == CS_NONCART else int(torch.tensor(self.shape).prod())
+        self.device = torch.device(device or "cuda")
+        self.stream = torch.cuda.current_stream(self.device)
+        g = Geom()
+        g.ndim = self.ndim
+        for i, s in enumerate(self.shape):
+            g.n[i] = s
+        g.ncoil = self.C
+        g.kind = self.kind
+        g.nsamp = int(nsamp)
+        g.sigma = float(sigma)
+        g.kwidth = int(kwidth)
+        g.beta = float(beta)
+        g.wav_levels = int(wav_levels)
+        self._ctx = ctypes.c_void_p()
+        rc = self.lib.cs_create(ctypes.byref(g), ctypes.c_void_p(self.stream.cuda_stream),
+                                ctypes.byref(self._ctx))
+        if rc != 0:
+            raise CSError(f"cs_create failed ({rc}): {self.lib.cs_last_error(None).decode()}")
+        self._keep = {}
+
+    # -- helpers -----------------------------------------------------------
+    def _check(self, rc, what):
+        if rc != 0:
+            msg = self.lib.cs_last_error(self._ctx).decode()
+            raise CSError(f"{what} failed ({rc}): {msg}")
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            self.lib.cs_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _img(self, t, name):
+        _need(t, torch.complex64, self.shape, name)
+
+    def _maps(self, maps, name="maps"):
+        _need(maps, torch.complex64, None, name)
+        if tuple(maps.shape[:-1]) != self.shape:
+            raise ValueError(f"{name} must have shape image + (ncoil,)")
+        return int(maps.shape[-1])
+
+    def _data(self, y, ncoil, name="y"):
+        _need(y, torch.complex64, None, name)
+        if self.kind == CS_CART:
+            ok = tuple(y.shape) == self.shape + (ncoil,)
+        else:
+            ok = tuple(y.shape) == (self.N, ncoil)
+        if not ok:
+            raise ValueError(f"{name} has shape {tuple(y.shape)}")
+
+    def empty_image(self):
+        return torch.empty(self.shape, dtype=torch.complex64, device=self.device)
+
+    def empty_data(self, ncoil):
+        if self.kind == CS_CART:
+            return torch.empty(self.shape + (ncoil,), dtype=torch.complex64, device=self.device)
+        return torch.empty((self.N, ncoil), dtype=torch.complex64, device=self.device)
+
+    # -- C ABI ----------------------------------------------------------------
+    def set_operator(self, maps, mask=None, coords=None, dcf=None):
+        self._maps(maps)
+        if self.kind == CS_CART:
+            _need(mask, torch.uint8, self.shape, "mask")
+        else:
+            _need(coords, torch.float32, (self.N, self.ndim), "coords")
+            if dcf is not None:
+                _need(dcf, torch.float32, (self.N,), "dcf")
+        self._keep["maps"] = maps
+        self._check(self.lib.cs_set_operator(self._ctx, _ptr(maps), _ptr(mask), _ptr(coords),
+                                             _ptr(dcf)), "cs_set_operator")
+
+    def sense_apply(self, maps, x, y=None):
+        nc = self._maps(maps)
+        self._img(x, "x")
+        y = self.empty_data(nc) if y is None else y
+        self._data(y, nc)
+        self._check(self.lib.sense_apply(self._ctx, _ptr(maps), nc, _ptr(x), _ptr(y)),
+                    "sense_apply")
+        return y
+
+    def sense_adjoint(self, maps, y, x=None):
+        nc = self._maps(maps)
+        self._data(y, nc)
+        x = self.empty_image() if x is None else x
+        self._img(x, "x")
+        self._check(self.lib.sense_adjoint(self._ctx, _ptr(maps), nc, _ptr(y), _ptr(x)),
+                    "sense_adjoint")
+        return x
+
+    def normal_apply(self, maps, x, out=None):
+        nc = self._maps(maps)
+        self._img(x, "x")
+        out = self.empty_image() if out is None else out
+        self._img(out, "out")
+        self._check(self.lib.normal_apply(self._ctx, _ptr(maps), nc, _ptr(x), _ptr(out)),
+                    "normal_apply")
+        return out
+
+    def sketch_build(self, y, V, S, seed, t, refresh=False, smaps=None, host_outputs=True):
+        self._data(y, self.C)
+        Ch = V + S
+        smaps = (torch.empty(self.shape + (Ch,), dtype=torch.complex64, device=self.device)
+                 if smaps is None else smaps)
+        _need(smaps, torch.complex64, self.shape + (Ch,), "smaps")
+        eig = U = signs = None
+        if host_outputs:
+            eig = (ctypes.c_double * self.C)()
+            U = (ctypes.c_double * (2 * self.C * self.C))()
+            signs = (ctypes.c_int8 * max(1, S * (self.C - V)))()
+        rc = self.lib.sketch_build(self._ctx, _ptr(y), int(V), int(S), ctypes.c_uint64(seed),
+                                   int(t), int(bool(refresh)), _ptr(smaps),
+                                   eig and ctypes.cast(eig, ctypes.c_void_p),
+                                   U and ctypes.cast(U, ctypes.c_void_p),
+                                   signs and ctypes.cast(signs, ctypes.c_void_p))
+        self._check(rc, "sketch_build")
+        if not host_outputs:
+            return smaps, None, None, None
+        import numpy as np
+        lam = np.array(eig[:], dtype=np.float64)
+        Uc = np.array(U[:], dtype=np.float64).reshape(self.C, self.C, 2)
+        Uc = Uc[..., 0] + 1j * Uc[..., 1]
+        sg = np.array(signs[:S * (self.C - V)], dtype=np.int8).reshape(S, self.C - V)
+        return smaps, lam, Uc, sg
+
+    def recon_run(self, y, mode="sketch", lam=1e-3, T=10, K=5, V=2, S=2, seed=0, t0=1,
+                  step=0.0, n_pow=30, reuse_b=False, x=None, x_ref=None):
+        self._data(y, self.C)
+        if x is None:
+            x = torch.zeros(self.shape, dtype=torch.complex64, device=self.device)
+        self._img(x, "x")
+        if x_ref is not None:
+            self._img(x_ref, "x_ref")
+        p = ReconParams()
+        p.mode = CS_RECON_SKETCH if mode == "sketch" else CS_RECON_FULL
+        p.lam = float(lam)
+        p.T, p.K, p.V, p.S = int(T), int(K), int(V), int(S)
+        p.seed = int(seed)
+        p.t0 = int(t0)
+        p.step = float(step)
+        p.n_pow = int(n_pow)
+        p.reuse_b = int(bool(reuse_b))
+        p.x_ref = None if x_ref is None else x_ref.data_ptr()
+        n = max(1, int(T))
+        dist = (ctypes.c_double * n)()
+        tms = (ctypes.c_double * n)()
+        st = ReconStats()
+        st.dist = ctypes.cast(dist, ctypes.POINTER(ctypes.c_double))
+        st.time_ms = ctypes.cast(tms, ctypes.POINTER(ctypes.c_double))
+        self._check(self.lib.recon_run(self._ctx, _ptr(y), ctypes.byref(p), _ptr(x),
+                                       ctypes.byref(st)), "recon_run")
+        return ReconResult(x=x, alpha=st.alpha, n_full_applies=st.n_full_applies,
+                           n_sketch_applies=st.n_sketch_applies, n_prox=st.n_prox,
+                           total_ms=st.total_ms, ms_full_normal=st.ms_full_normal,
+                           ms_sketch_normal=st.ms_sketch_normal, ms_prox=st.ms_prox,
+                           ms_sketch=st.ms_sketch, time_ms=list(tms[:T]),
+                           dist=list(dist[:T]) if x_ref is not None else [])
+
+    def prox_l1wav(self, v, tau, out=None):
+        self._img(v, "v")
+        out = self.empty_image() if out is None else out
+        self._check(self.lib.cs_prox_l1wav(self._ctx, _ptr(v), ctypes.c_float(tau), _ptr(out)),
+                    "cs_prox_l1wav")
+        return out
+
+    def dwt(self, x, out=None):
+        self._img(x, "x")
+        out = self.empty_image() if out is None else out
+        self._check(self.lib.cs_dwt(self._ctx, _ptr(x), _ptr(out)), "cs_dwt")
+        return out
+
+    def idwt(self, c, out=None):
+        self._img(c, "coef")
+        out = self.empty_image() if out is None else out
+        self._check(self.lib.cs_idwt(self._ctx, _ptr(c), _ptr(out)), "cs_idwt")
+        return out
+
+    def coil_mix(self, inp, M, out=None):
+        """out[..., j] = sum_c inp[..., c] M[j, c] (M: complex numpy [cout, cin])."""
+        import numpy as np
+        cin = self._maps(inp, "inp")
+        M = np.ascontiguousarray(np.asarray(M, dtype=np.complex128))
+        cout = M.shape[0]
+        if M.shape != (cout, cin):
+            raise ValueError("M must be [cout, cin]")
+        Mr = np.ascontiguousarray(np.stack([M.real, M.imag], -1))
+        out = (torch.empty(self.shape + (cout,), dtype=torch.complex64, device=self.device)
+               if out is None else out)
+        _need(out, torch.complex64, self.shape + (cout,), "out")
+        self._check(self.lib.cs_coil_mix(self._ctx, _ptr(inp), cin,
+                                         Mr.ctypes.data_as(ctypes.c_void_p), cout, _ptr(out)),
+                    "cs_coil_mix")
+        return out
+
+    def dot(self, a, b):
+        self._img(a, "a")
+        self._img(b, "b")
+        out = (ctypes.c_double * 2)()
+        self._check(self.lib.cs_dot(self._ctx, _ptr(a), _ptr(b), ctypes.cast(out, ctypes.c_void_p)),
+                    "cs_dot")
+        return complex(out[0], out[1])
+
+    def power_iteration(self, maps, n_iter=30):
+        nc = self._maps(maps)
+        L = ctypes.c_double()
+        self._check(self.lib.cs_power_iteration(self._ctx, _ptr(maps), nc, int(n_iter),
+                                                ctypes.byref(L)), "cs_power_iteration")
+        return L.value
+
+    def grid_shape(self):
+        m = (ctypes.c_int * 3)()
+        self._check(self.lib.cs_grid_shape(self._ctx, ctypes.cast(m, ctypes.c_void_p)),
+                    "cs_grid_shape")
+        return tuple(m[:])
+
+    def profile_enable(self, on=True):
+        self._check(self.lib.cs_profile_enable(self._ctx, int(bool(on))), "cs_profile_enable")
+
+    def profile_read(self):
+        """{kernel kind: (total ms, launches)} since the last read."""
+        ms = (ctypes.c_double * NKERNELS)()
+        cnt = (ctypes.c_longlong * NKERNELS)()
+        self._check(self.lib.cs_profile_read(self._ctx, ctypes.cast(ms, ctypes.c_void_p),
+                                             ctypes.cast(cnt, ctypes.c_void_p)),
+                    "cs_profile_read")
+        return {KERNEL_KINDS[i]: (ms[i], cnt[i]) for i in range(NKERNELS)}

@@ -1,0 +1,884 @@
+// C ABI of the coil-sketching library: contexts, the SENSE operator and its
+// adjoint / normal operator (Sec. 2.1, Eqs. 1-2, 5), the structured sketch
+// (Sec. 2.3.2-2.3.3, Eqs. 11-13) and Algorithm 1 with FISTA inner solves
+// (Sec. 2.3.4, Sec. 3.3.1).
+#include <cmath>
+#include <cstring>
+
+#include "cs_internal.h"
+
+namespace {
+std::string g_create_error;
+
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): output number n from state
+// seed is mix(seed + n * 0x9E3779B97F4A7C15).
+uint64_t splitmix64_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+// Rademacher block of outer iteration t: entry (a, b) is -1 when the top bit
+// of output number ((t << 32) | (a * cols + b)) + 1 is set, else +1.
+void rademacher(uint64_t seed, int t, int S, int cols, std::vector<int8_t>& out) {
+  out.resize((size_t)S * cols);
+  for (int a = 0; a < S; ++a)
+    for (int b = 0; b < cols; ++b) {
+      const uint64_t ctr = ((uint64_t)(uint32_t)t << 32) | (uint64_t)(a * cols + b);
+      const uint64_t z = splitmix64_mix(seed + (ctr + 1) * 0x9E3779B97F4A7C15ULL);
+      out[(size_t)a * cols + b] = (z >> 63) ? -1 : 1;
+    }
+}
+}  // namespace
+
+namespace cs {
+
+int fail(cs_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_error = msg;
+  return code;
+}
+
+namespace {
+hipEvent_t pool_event(cs_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+void prof_begin(cs_ctx* c, int kind) {
+  if (!c->prof) return;
+  cs_ctx::ProfRec r{kind, pool_event(c), pool_event(c)};
+  if (!r.a || !r.b) return;
+  (void)hipEventRecord(r.a, c->stream);
+  c->prof_recs.push_back(r);
+}
+
+void prof_end(cs_ctx* c) {
+  if (!c->prof || c->prof_recs.empty()) return;
+  (void)hipEventRecord(c->prof_recs.back().b, c->stream);
+}
+
+namespace {
+
+PassArgs blank(int cb) {
+  PassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.cb = cb;
+  a.src_ldc = cb;
+  a.dst_ldc = cb;
+  return a;
+}
+
+int with_plan(cs_ctx* c, PassArgs& a, int L) {
+  const FFTPlan* p = nullptr;
+  CS_TRY(get_plan(c, L, &p));
+  fill_plan(a, p);
+  return CS_OK;
+}
+
+// ---- Cartesian (2D): F~ = U F~_u, unitary FFT, zero-filled data -----------
+
+// y pass from the image: x * maps / sqrt(D) -> FFT_y -> grid [ny][nx][cb]
+// (or, with a ky-only mask, the whole normal operator in one pass)
+int cart_first(cs_ctx* c, const float2* x, const float2* maps, int ldc, int c0, int cb,
+               float2* dst, bool fused_normal, float2* out) {
+  PassArgs a = blank(cb);
+  CS_TRY(with_plan(c, a, c->ny));
+  a.n_in = a.n_out = c->ny;
+  a.dir = -1;
+  a.inner = (long long)c->nx * cb;
+  a.prologue = PRO_IMAGE;
+  a.img = x;
+  a.maps = maps;
+  a.maps_ldc = ldc;
+  a.maps_c0 = c0;
+  a.P = c->nx;
+  a.da = c->da[1];
+  a.dp = c->dp_y;
+  if (fused_normal) {
+    // F_x^H F_x = I: only the unitary y transform pair remains
+    a.da = c->da_y1d;
+    a.mid = MID_MASK_IFFT;
+    a.mask = c->mask;
+    a.mask_os = 0;
+    a.mask_rs = c->nx;
+    a.epilogue = EPI_IMAGE;
+    a.img_out = out;
+    a.accumulate = c0 > 0;
+  } else {
+    a.dst = dst;
+    a.dst_rs = (long long)c->nx * cb;
+  }
+  return launch_pass(c, a, 1);
+}
+
+// y pass to the image: IFFT_y -> conj(maps) sum / sqrt(D)
+int cart_last(cs_ctx* c, const float2* src, const float2* maps, int ldc, int c0, int cb,
+              float2* out) {
+  PassArgs a = blank(cb);
+  CS_TRY(with_plan(c, a, c->ny));
+  a.n_in = a.n_out = c->ny;
+  a.dir = +1;
+  a.inner = (long long)c->nx * cb;
+  a.src = src;
+  a.src_rs = (long long)c->nx * cb;
+  a.epilogue = EPI_IMAGE;
+  a.img_out = out;
+  a.accumulate = c0 > 0;
+  a.maps = maps;
+  a.maps_ldc = ldc;
+  a.maps_c0 = c0;
+  a.P = c->nx;
+  a.da = c->da[1];
+  a.dp = c->dp_y;
+  return launch_pass(c, a, 1);
+}
+
+// x pass over rows ky: mode 0 = FFT, mask, IFFT (normal); 1 = FFT, mask -> y;
+// 2 = mask y, IFFT (adjoint)
+int cart_xpass(cs_ctx* c, int mode, const float2* src, long long src_os, long long src_rs,
+               int src_ldc, int src_c0, float2* dst, long long dst_os, long long dst_rs,
+               int dst_ldc, int dst_c0, int cb) {
+  PassArgs a = blank(cb);
+  CS_TRY(with_plan(c, a, c->nx));
+  a.n_in = a.n_out = c->nx;
+  a.inner = cb;
+  a.src = src; a.src_os = src_os; a.src_rs = src_rs; a.src_ldc = src_ldc; a.src_c0 = src_c0;
+  a.dst = dst; a.dst_os = dst_os; a.dst_rs = dst_rs; a.dst_ldc = dst_ldc; a.dst_c0 = dst_c0;
+  a.mask = c->mask;
+  a.mask_os = c->nx;
+  a.mask_rs = 1;
+  if (mode == 0) { a.dir = -1; a.mid = MID_MASK_IFFT; }
+  if (mode == 1) { a.dir = -1; a.mid = MID_MASK; }
+  if (mode == 2) { a.dir = +1; a.premask = 1; }
+  return launch_pass(c, a, c->ny);
+}
+
+int cart_normal(cs_ctx* c, const float2* maps, int ldc, int c0, int cb, const float2* x,
+                float2* out) {
+  if (c->mask1d) return cart_first(c, x, maps, ldc, c0, cb, nullptr, true, out);
+  const long long row = (long long)c->nx * cb;
+  CS_TRY(cart_first(c, x, maps, ldc, c0, cb, c->gridA, false, nullptr));
+  CS_TRY(cart_xpass(c, 0, c->gridA, row, cb, cb, 0, c->gridA, row, cb, cb, 0, cb));
+  return cart_last(c, c->gridA, maps, ldc, c0, cb, out);
+}
+
+int cart_apply(cs_ctx* c, const float2* maps, int ldc, int c0, int cb, const float2* x,
+               float2* y) {
+  const long long row = (long long)c->nx * cb;
+  CS_TRY(cart_first(c, x, maps, ldc, c0, cb, c->gridA, false, nullptr));
+  return cart_xpass(c, 1, c->gridA, row, cb, cb, 0, y, (long long)c->nx * ldc, ldc, ldc, c0,
+                    cb);
+}
+
+int cart_adjoint(cs_ctx* c, const float2* maps, int ldc, int c0, int cb, const float2* y,
+                 float2* out) {
+  const long long row = (long long)c->nx * cb;
+  CS_TRY(cart_xpass(c, 2, y, (long long)c->nx * ldc, ldc, ldc, c0, c->gridA, row, cb, cb, 0,
+                    cb));
+  return cart_last(c, c->gridA, maps, ldc, c0, cb, out);
+}
+
+// ---- non-Cartesian: deapodise, zero-pad, FFT on the sigma-grid, KB gridding --
+
+// forward passes image -> oversampled grid [mz][my][mx][cb]; returns the buffer
+int nc_forward(cs_ctx* c, const float2* x, const float2* maps, int ldc, int c0, int cb,
+               float2** result) {
+  const int nz = c->nz, ny = c->ny, nx = c->nx, mz = c->mz, my = c->my, mx = c->mx;
+  float2* A = c->gridA;
+  float2* B = c->gridB;
+  if (c->ndim == 3) {
+    PassArgs a = blank(cb);  // z
+    CS_TRY(with_plan(c, a, mz));
+    a.n_in = nz; a.pad_in = 1; a.n_out = mz; a.dir = -1;
+    a.inner = (long long)ny * nx * cb;
+    a.prologue = PRO_IMAGE; a.img = x; a.maps = maps; a.maps_ldc = ldc; a.maps_c0 = c0;
+    a.P = (long long)ny * nx; a.da = c->da[0]; a.dp = c->dp_z;
+    a.dst = A; a.dst_rs = (long long)ny * nx * cb;
+    CS_TRY(launch_pass(c, a, 1));
+    PassArgs b = blank(cb);  // y
+    CS_TRY(with_plan(c, b, my));
+    b.n_in = ny; b.pad_in = 1; b.n_out = my; b.dir = -1;
+    b.inner = (long long)nx * cb;
+    b.src = A; b.src_os = (long long)ny * nx * cb; b.src_rs = (long long)nx * cb;
+    b.dst = B; b.dst_os = (long long)my * nx * cb; b.dst_rs = (long long)nx * cb;
+    CS_TRY(launch_pass(c, b, mz));
+    PassArgs d = blank(cb);  // x
+    CS_TRY(with_plan(c, d, mx));
+    d.n_in = nx; d.pad_in = 1; d.n_out = mx; d.dir = -1;
+    d.inner = cb;
+    d.src = B; d.src_os = (long long)nx * cb; d.src_rs = cb;
+    d.dst = A; d.dst_os = (long long)mx * cb; d.dst_rs = cb;
+    CS_TRY(launch_pass(c, d, (long long)mz * my));
+    *result = A;
+  } else {
+    PassArgs a = blank(cb);  // y
+    CS_TRY(with_plan(c, a, my));
+    a.n_in = ny; a.pad_in = 1; a.n_out = my; a.dir = -1;
+    a.inner = (long long)nx * cb;
+    a.prologue = PRO_IMAGE; a.img = x; a.maps = maps; a.maps_ldc = ldc; a.maps_c0 = c0;
+    a.P = nx; a.da = c->da[1]; a.dp = c->dp_y;
+    a.dst = A; a.dst_rs = (long long)nx * cb;
+    CS_TRY(launch_pass(c, a, 1));
+    PassArgs d = blank(cb);  // x
+    CS_TRY(with_plan(c, d, mx));
+    d.n_in = nx; d.pad_in = 1; d.n_out = mx; d.dir = -1;
+    d.inner = cb;
+    d.src = A; d.src_os = (long long)nx * cb; d.src_rs = cb;
+    d.dst = B; d.dst_os = (long long)mx * cb; d.dst_rs = cb;
+    CS_TRY(launch_pass(c, d, my));
+    *result = B;
+  }
+  return CS_OK;
+}
+
+// adjoint passes grid G [mz][my][mx][cb] -> image (conj-map coil sum); `tmp`
+// is the other grid buffer; G is overwritten
+int nc_adjoint_grid(cs_ctx* c, float2* G, float2* tmp, const float2* maps, int ldc, int c0,
+                    int cb, float2* out) {
+  const int nz = c->nz, ny = c->ny, nx = c->nx, mz = c->mz, my = c->my, mx = c->mx;
+  PassArgs d = blank(cb);  // x
+  CS_TRY(with_plan(c, d, mx));
+  d.n_in = mx; d.n_out = nx; d.pad_out = 1; d.dir = +1;
+  d.inner = cb;
+  d.src = G; d.src_os = (long long)mx * cb; d.src_rs = cb;
+  d.dst = tmp; d.dst_os = (long long)nx * cb; d.dst_rs = cb;
+  CS_TRY(launch_pass(c, d, (long long)mz * my));
+  if (c->ndim == 3) {
+    PassArgs b = blank(cb);  // y
+    CS_TRY(with_plan(c, b, my));
+    b.n_in = my; b.n_out = ny; b.pad_out = 1; b.dir = +1;
+    b.inner = (long long)nx * cb;
+    b.src = tmp; b.src_os = (long long)my * nx * cb; b.src_rs = (long long)nx * cb;
+    b.dst = G; b.dst_os = (long long)ny * nx * cb; b.dst_rs = (long long)nx * cb;
+    CS_TRY(launch_pass(c, b, mz));
+    PassArgs a = blank(cb);  // z
+    CS_TRY(with_plan(c, a, mz));
+    a.n_in = mz; a.n_out = nz; a.pad_out = 1; a.dir = +1;
+    a.inner = (long long)ny * nx * cb;
+    a.src = G; a.src_rs = (long long)ny * nx * cb;
+    a.epilogue = EPI_IMAGE; a.img_out = out; a.accumulate = c0 > 0;
+    a.maps = maps; a.maps_ldc = ldc; a.maps_c0 = c0;
+    a.P = (long long)ny * nx; a.da = c->da[0]; a.dp = c->dp_z;
+    return launch_pass(c, a, 1);
+  }
+  PassArgs a = blank(cb);  // y
+  CS_TRY(with_plan(c, a, my));
+  a.n_in = my; a.n_out = ny; a.pad_out = 1; a.dir = +1;
+  a.inner = (long long)nx * cb;
+  a.src = tmp; a.src_rs = (long long)nx * cb;
+  a.epilogue = EPI_IMAGE; a.img_out = out; a.accumulate = c0 > 0;
+  a.maps = maps; a.maps_ldc = ldc; a.maps_c0 = c0;
+  a.P = nx; a.da = c->da[1]; a.dp = c->dp_y;
+  return launch_pass(c, a, 1);
+}
+
+int nc_normal(cs_ctx* c, const float2* maps, int ldc, int c0, int cb, const float2* x,
+              float2* out) {
+  float2* G = nullptr;
+  CS_TRY(nc_forward(c, x, maps, ldc, c0, cb, &G));
+  float2* other = G == c->gridA ? c->gridB : c->gridA;
+  CS_TRY(launch_interp(c, G, cb, W_FULL, c->vbuf, cb, 0, 0));
+  CS_TRY(launch_spread(c, c->vbuf, cb, other));
+  return nc_adjoint_grid(c, other, G, maps, ldc, c0, cb, out);
+}
+
+int nc_apply(cs_ctx* c, const float2* maps, int ldc, int c0, int cb, const float2* x,
+             float2* y) {
+  float2* G = nullptr;
+  CS_TRY(nc_forward(c, x, maps, ldc, c0, cb, &G));
+  return launch_interp(c, G, cb, W_SQRT, y, ldc, c0, 1);
+}
+
+int nc_adjoint(cs_ctx* c, const float2* maps, int ldc, int c0, int cb, const float2* y,
+               float2* out) {
+  CS_TRY(launch_gather_samples(c, y, ldc, c0, cb, c->vbuf));
+  CS_TRY(launch_spread(c, c->vbuf, cb, c->gridA));
+  return nc_adjoint_grid(c, c->gridA, c->gridB, maps, ldc, c0, cb, out);
+}
+
+int check_ready(cs_ctx* c, const void* maps, int ncoil, const void* a, const void* b) {
+  if (!c) return CS_EINVAL;
+  if (!c->have_op) return fail(c, CS_EINVAL, "cs_set_operator has not been called");
+  if (!maps || !a || !b) return fail(c, CS_EINVAL, "null pointer");
+  if (ncoil < 1 || ncoil > 64) return fail(c, CS_EINVAL, "ncoil must be in [1, 64]");
+  return CS_OK;
+}
+
+int chunk_loop(cs_ctx* c, int ncoil,
+               int (*fn)(cs_ctx*, const float2*, int, int, int, const float2*, float2*),
+               const float2* maps, const float2* in, float2* out) {
+  const int chunk = c->g.kind == CS_NONCART ? kCoilChunk : kCoilChunk;
+  for (int c0 = 0; c0 < ncoil; c0 += chunk) {
+    const int cb = std::min(chunk, ncoil - c0);
+    CS_TRY(fn(c, maps, ncoil, c0, cb, in, out));
+  }
+  return CS_OK;
+}
+
+int op_apply(cs_ctx* c, const float2* maps, int ldc, int c0, int cb, const float2* x,
+             float2* y) {
+  return c->g.kind == CS_CART ? cart_apply(c, maps, ldc, c0, cb, x, y)
+                              : nc_apply(c, maps, ldc, c0, cb, x, y);
+}
+int op_adjoint(cs_ctx* c, const float2* maps, int ldc, int c0, int cb, const float2* y,
+               float2* x) {
+  return c->g.kind == CS_CART ? cart_adjoint(c, maps, ldc, c0, cb, y, x)
+                              : nc_adjoint(c, maps, ldc, c0, cb, y, x);
+}
+int op_normal_chunk(cs_ctx* c, const float2* maps, int ldc, int c0, int cb,
+                    const float2* x, float2* out) {
+  return c->g.kind == CS_CART ? cart_normal(c, maps, ldc, c0, cb, x, out)
+                              : nc_normal(c, maps, ldc, c0, cb, x, out);
+}
+
+int upload_table(cs_ctx* c, float** dst, const std::vector<float>& v) {
+  CS_HIP(c, hipMalloc(dst, sizeof(float) * std::max<size_t>(1, v.size())));
+  CS_HIP(c, hipMemcpy(*dst, v.data(), sizeof(float) * v.size(), hipMemcpyHostToDevice));
+  return CS_OK;
+}
+
+int create_impl(const cs_geom* g, void* stream, cs_ctx** out) {
+  if (!g || !out) return fail(nullptr, CS_EINVAL, "null argument");
+  *out = nullptr;
+  if (g->ndim != 2 && g->ndim != 3) return fail(nullptr, CS_EINVAL, "ndim must be 2 or 3");
+  if (g->ncoil < 1 || g->ncoil > 64) return fail(nullptr, CS_EINVAL, "ncoil must be in [1, 64]");
+  if (g->kind != CS_CART && g->kind != CS_NONCART) return fail(nullptr, CS_EINVAL, "kind");
+  if (g->kind == CS_CART && g->ndim != 2)
+    return fail(nullptr, CS_EUNSUPPORTED, "Cartesian operator is 2D only");
+  for (int a = 0; a < g->ndim; ++a)
+    if (g->n[a] < 4 || g->n[a] > kMaxFFT) return fail(nullptr, CS_EINVAL, "image size");
+  if (g->kind == CS_NONCART) {
+    if (g->kwidth != 4) return fail(nullptr, CS_EUNSUPPORTED, "only kernel width 4");
+    if (!(g->sigma >= 1.0f && g->sigma <= 3.0f)) return fail(nullptr, CS_EINVAL, "sigma");
+    if (g->nsamp < 0 || g->nsamp > 0x7fffffffLL) return fail(nullptr, CS_EINVAL, "nsamp");
+  }
+  if (g->wav_levels < 0 || g->wav_levels > 10) return fail(nullptr, CS_EINVAL, "wav_levels");
+  for (int a = 0; a < g->ndim; ++a)
+    if (g->n[a] % (1 << g->wav_levels) != 0)
+      return fail(nullptr, CS_EINVAL, "image size not divisible by 2^wav_levels");
+
+  cs_ctx* c = new cs_ctx();
+  c->g = *g;
+  c->stream = (hipStream_t)stream;
+  c->ndim = g->ndim;
+  c->C = g->ncoil;
+  if (g->ndim == 3) {
+    c->nz = g->n[0]; c->ny = g->n[1]; c->nx = g->n[2];
+  } else {
+    c->nz = 1; c->ny = g->n[0]; c->nx = g->n[1];
+  }
+  c->D = (long long)c->nz * c->ny * c->nx;
+  if (g->kind == CS_NONCART) {
+    auto m = [&](int n) { return (int)std::lround((double)g->sigma * n); };
+    c->mz = g->ndim == 3 ? m(c->nz) : 1;
+    c->my = m(c->ny);
+    c->mx = m(c->nx);
+    c->N = g->nsamp;
+    const double W = 4.0, s = g->sigma;
+    c->beta = g->beta > 0 ? g->beta
+                          : (float)(M_PI * std::sqrt((W / s) * (W / s) * (s - 0.5) * (s - 0.5) - 0.8));
+  } else {
+    c->mz = c->nz; c->my = c->ny; c->mx = c->nx;
+    c->N = c->D;
+  }
+  c->M = (long long)c->mz * c->my * c->mx;
+  int rc = CS_OK;
+  auto alloc = [&](void** p, size_t bytes) -> int {
+    hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 16));
+    if (e != hipSuccess) return fail(c, CS_EHIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+    return CS_OK;
+  };
+  const size_t f2 = sizeof(float2);
+  if ((rc = alloc((void**)&c->gridA, f2 * c->M * kCoilChunk)) ||
+      (rc = alloc((void**)&c->gridB, f2 * c->M * kCoilChunk)) ||
+      (rc = alloc((void**)&c->red, sizeof(double) * 2 * 1024)) ||
+      (rc = alloc((void**)&c->red_out, sizeof(double) * 2 * 1024)) ||
+      (rc = alloc((void**)&c->cov_part, sizeof(double) * 2 * 512 * c->C * c->C)) ||
+      (rc = alloc((void**)&c->cov, sizeof(double) * 2 * c->C * c->C)) ||
+      (rc = alloc((void**)&c->eig_dev, sizeof(double) * (2 * c->C * c->C + c->C))) ||
+      (rc = alloc((void**)&c->vmaps, f2 * c->D * c->C)) ||
+      (rc = alloc((void**)&c->smaps, f2 * c->D * c->C)) ||
+      (rc = alloc((void**)&c->wav1, f2 * c->D)) ||
+      (rc = alloc((void**)&c->wav2, f2 * c->D))) {
+    cs_destroy(c);
+    g_create_error = "allocation failed";
+    return rc;
+  }
+  if (g->kind == CS_NONCART && (rc = alloc((void**)&c->vbuf, f2 * std::max(1LL, c->N) * kCoilChunk))) {
+    cs_destroy(c);
+    g_create_error = "allocation failed";
+    return rc;
+  }
+  for (int i = 0; i < 10; ++i) {
+    float2* p = nullptr;
+    if ((rc = alloc((void**)&p, f2 * c->D))) {
+      cs_destroy(c);
+      g_create_error = "allocation failed";
+      return rc;
+    }
+    c->img.push_back(p);
+  }
+  if (hipHostMalloc((void**)&c->host_red, sizeof(double) * 2 * 1024) != hipSuccess) {
+    cs_destroy(c);
+    g_create_error = "hipHostMalloc failed";
+    return CS_EHIP;
+  }
+  // scale tables: the first pass axis carries 1/sqrt(D); the non-Cartesian
+  // operator divides by the KB transform Phi(r / m) per axis
+  const double isd = 1.0 / std::sqrt((double)c->D);
+  const int n3[3] = {c->nz, c->ny, c->nx};
+  const int m3[3] = {c->mz, c->my, c->mx};
+  std::vector<float> tab[3];
+  for (int a = 0; a < 3; ++a) {
+    tab[a].resize(n3[a]);
+    for (int t = 0; t < n3[a]; ++t) {
+      double v = 1.0;
+      if (g->kind == CS_NONCART && !(a == 0 && c->ndim == 2))
+        v = 1.0 / kb_ft((double)(t - n3[a] / 2) / (double)m3[a], 4.0, c->beta);
+      tab[a][t] = (float)v;
+    }
+  }
+  const int first = c->ndim == 3 ? 0 : 1;
+  for (auto& v : tab[first]) v = (float)((double)v * isd);
+  // per-pixel tables of the axes after the first
+  std::vector<float> dpz((size_t)c->ny * c->nx), dpy(c->nx), y1d(c->ny);
+  for (int y = 0; y < c->ny; ++y) y1d[y] = (float)(1.0 / std::sqrt((double)c->ny));
+  for (int y = 0; y < c->ny; ++y)
+    for (int x = 0; x < c->nx; ++x) dpz[(size_t)y * c->nx + x] = tab[1][y] * tab[2][x];
+  for (int x = 0; x < c->nx; ++x) dpy[x] = tab[2][x];
+  if ((rc = upload_table(c, &c->da[0], tab[0])) || (rc = upload_table(c, &c->da[1], tab[1])) ||
+      (rc = upload_table(c, &c->da[2], tab[2])) || (rc = upload_table(c, &c->dp_z, dpz)) ||
+      (rc = upload_table(c, &c->dp_y, dpy)) || (rc = upload_table(c, &c->da_y1d, y1d)) ||
+      (rc = wavelet_init(c))) {
+    std::string e = c->err;
+    cs_destroy(c);
+    g_create_error = e;
+    return rc;
+  }
+  *out = c;
+  return CS_OK;
+}
+
+int power_iter(cs_ctx* c, const float2* maps, int ncoil, int n_iter, double* L) {
+  float2* v = c->img[8];
+  float2* w = c->img[9];
+  CS_TRY(vec_fill(c, v, c->D, (float)(1.0 / std::sqrt((double)c->D)), 0.f));
+  for (int i = 0; i < n_iter; ++i) {
+    CS_TRY(op_normal(c, maps, ncoil, v, w));
+    double d[2];
+    CS_TRY(vec_dot(c, w, w, c->D, d));
+    const double nrm = std::sqrt(d[0]);
+    if (!(nrm > 0) || !std::isfinite(nrm)) return fail(c, CS_ENUMERIC, "power iteration norm");
+    CS_TRY(vec_axpby(c, v, (float)(1.0 / nrm), w, 0.f, w, c->D));
+  }
+  CS_TRY(op_normal(c, maps, ncoil, v, w));
+  double d[2];
+  CS_TRY(vec_dot(c, w, w, c->D, d));
+  *L = std::sqrt(d[0]);
+  return CS_OK;
+}
+
+int sketch_impl(cs_ctx* c, const float2* y, int V, int S, uint64_t seed, int t, int refresh,
+                float2* smaps, std::vector<int8_t>* signs_out) {
+  const int C = c->C;
+  if (V < 0 || S < 0 || V + S < 1 || V + S > C || (S == 0 && V != C))
+    return fail(c, CS_EINVAL, "sketch sizes: need 0 < V + S <= C and S > 0 unless V = C");
+  if (!c->have_U || refresh) {
+    if (!y) return fail(c, CS_EINVAL, "y is required for the first sketch");
+    CS_TRY(covariance_eig(c, y));
+    // virtual maps c'[d][j] = sum_c conj(U[c][j]) c[d][c]
+    std::vector<double> M((size_t)2 * C * C);
+    for (int j = 0; j < C; ++j)
+      for (int cc = 0; cc < C; ++cc) {
+        M[2 * (j * C + cc)] = c->U[2 * (cc * C + j)];
+        M[2 * (j * C + cc) + 1] = -c->U[2 * (cc * C + j) + 1];
+      }
+    CS_TRY(coil_mix(c, c->maps, C, 0, C, M.data(), C, c->vmaps, C, 0, 1.0f));
+    c->have_U = true;
+  }
+  const int Ch = V + S;
+  if (V > 0) {
+    std::vector<double> I((size_t)2 * V * V, 0.0);
+    for (int j = 0; j < V; ++j) I[2 * (j * V + j)] = 1.0;
+    CS_TRY(coil_mix(c, c->vmaps, C, 0, V, I.data(), V, smaps, Ch, 0, 1.0f));
+  }
+  std::vector<int8_t> sg;
+  if (S > 0) {
+    const int cols = C - V;
+    rademacher(seed, t, S, cols, sg);
+    std::vector<double> R((size_t)2 * S * cols, 0.0);
+    for (int a = 0; a < S; ++a)
+      for (int b = 0; b < cols; ++b) R[2 * (a * cols + b)] = (double)sg[(size_t)a * cols + b];
+    CS_TRY(coil_mix(c, c->vmaps, C, V, cols, R.data(), S, smaps, Ch, V,
+                    (float)(1.0 / std::sqrt((double)S))));
+  }
+  if (signs_out) *signs_out = sg;
+  return CS_OK;
+}
+
+}  // namespace
+
+int op_normal(cs_ctx* c, const float2* maps, int ncoil, const float2* x, float2* out) {
+  for (int c0 = 0; c0 < ncoil; c0 += kCoilChunk) {
+    const int cb = std::min(kCoilChunk, ncoil - c0);
+    CS_TRY(op_normal_chunk(c, maps, ncoil, c0, cb, x, out));
+  }
+  return CS_OK;
+}
+
+}  // namespace cs
+
+using namespace cs;
+
+extern "C" {
+
+int cs_create(const cs_geom* g, void* stream, cs_ctx** out) {
+  return create_impl(g, stream, out);
+}
+
+void cs_destroy(cs_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  auto fr = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  fr(c->gridA); fr(c->gridB); fr(c->vbuf); fr(c->red); fr(c->red_out);
+  fr(c->cov_part); fr(c->cov); fr(c->eig_dev); fr(c->vmaps); fr(c->smaps);
+  fr(c->wav1); fr(c->wav2); fr(c->mask); fr(c->rec); fr(c->dcf_orig);
+  fr(c->tile_off); fr(c->tile_list); fr(c->mixB); fr(c->ones);
+  for (int a = 0; a < 3; ++a) fr(c->da[a]);
+  fr(c->dp_z); fr(c->dp_y); fr(c->da_y1d);
+  for (auto* p : c->img) fr(p);
+  for (auto& kv : c->plans) fr(kv.second.tw);
+  if (c->host_red) (void)hipHostFree(c->host_red);
+  for (auto& r : c->prof_recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char* cs_last_error(const cs_ctx* c) {
+  return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+int cs_set_operator(cs_ctx* c, const void* maps, const uint8_t* mask, const float* coords,
+                    const float* dcf) {
+  if (!c) return CS_EINVAL;
+  if (!maps) return fail(c, CS_EINVAL, "maps is null");
+  CS_HIP(c, hipStreamSynchronize(c->stream));
+  c->maps = (const float2*)maps;
+  c->have_U = false;
+  c->have_b = false;
+  if (c->g.kind == CS_CART) {
+    if (!mask) return fail(c, CS_EINVAL, "Cartesian operator needs a mask");
+    std::vector<uint8_t> h(c->D);
+    CS_HIP(c, hipMemcpy(h.data(), mask, c->D, hipMemcpyDeviceToHost));
+    bool oned = true;
+    for (int y = 0; y < c->ny && oned; ++y)
+      for (int x = 1; x < c->nx; ++x)
+        if ((h[(size_t)y * c->nx + x] != 0) != (h[(size_t)y * c->nx] != 0)) {
+          oned = false;
+          break;
+        }
+    for (auto& v : h) v = v ? 1 : 0;
+    if (!c->mask) CS_HIP(c, hipMalloc(&c->mask, c->D));
+    CS_HIP(c, hipMemcpy(c->mask, h.data(), c->D, hipMemcpyHostToDevice));
+    c->mask1d = oned;
+  } else {
+    if (!coords) return fail(c, CS_EINVAL, "non-Cartesian operator needs coordinates");
+    if (c->rec) {
+      CS_HIP(c, hipFree(c->rec)); c->rec = nullptr;
+      CS_HIP(c, hipFree(c->tile_off)); c->tile_off = nullptr;
+      CS_HIP(c, hipFree(c->tile_list)); c->tile_list = nullptr;
+    }
+    if (c->dcf_orig) {
+      CS_HIP(c, hipFree(c->dcf_orig));
+      c->dcf_orig = nullptr;
+    }
+    CS_TRY(setup_noncart(c, coords, dcf));
+  }
+  c->have_op = true;
+  return CS_OK;
+}
+
+int sense_apply(cs_ctx* c, const void* maps, int ncoil, const void* x, void* y) {
+  CS_TRY(check_ready(c, maps, ncoil, x, y));
+  return chunk_loop(c, ncoil, op_apply, (const float2*)maps, (const float2*)x, (float2*)y);
+}
+
+int sense_adjoint(cs_ctx* c, const void* maps, int ncoil, const void* y, void* x) {
+  CS_TRY(check_ready(c, maps, ncoil, y, x));
+  return chunk_loop(c, ncoil, op_adjoint, (const float2*)maps, (const float2*)y, (float2*)x);
+}
+
+int normal_apply(cs_ctx* c, const void* maps, int ncoil, const void* x, void* out) {
+  CS_TRY(check_ready(c, maps, ncoil, x, out));
+  if (x == out) return fail(c, CS_EINVAL, "x and out must not alias");
+  return op_normal(c, (const float2*)maps, ncoil, (const float2*)x, (float2*)out);
+}
+
+int sketch_build(cs_ctx* c, const void* y, int V, int S, uint64_t seed, int t, int refresh,
+                 void* smaps, double* eig, double* U_out, int8_t* signs) {
+  if (!c) return CS_EINVAL;
+  if (!c->have_op) return fail(c, CS_EINVAL, "cs_set_operator has not been called");
+  if (!smaps) return fail(c, CS_EINVAL, "smaps is null");
+  std::vector<int8_t> sg;
+  CS_TRY(sketch_impl(c, (const float2*)y, V, S, seed, t, refresh, (float2*)smaps, &sg));
+  if (eig) std::memcpy(eig, c->lam.data(), sizeof(double) * c->C);
+  if (U_out) std::memcpy(U_out, c->U.data(), sizeof(double) * 2 * c->C * c->C);
+  if (signs && !sg.empty()) std::memcpy(signs, sg.data(), sg.size());
+  if (eig || U_out || signs) CS_HIP(c, hipStreamSynchronize(c->stream));
+  return CS_OK;
+}
+
+int cs_prox_l1wav(cs_ctx* c, const void* v, float tau, void* out) {
+  if (!c || !v || !out) return CS_EINVAL;
+  return prox_l1(c, (const float2*)v, tau, (float2*)out);
+}
+
+int cs_dwt(cs_ctx* c, const void* x, void* coef) {
+  if (!c || !x || !coef) return CS_EINVAL;
+  return dwt_fwd(c, (const float2*)x, (float2*)coef);
+}
+
+int cs_idwt(cs_ctx* c, const void* coef, void* x) {
+  if (!c || !x || !coef) return CS_EINVAL;
+  return dwt_inv(c, (const float2*)coef, (float2*)x);
+}
+
+int cs_coil_mix(cs_ctx* c, const void* in, int cin, const double* M, int cout, void* out) {
+  if (!c || !in || !M || !out) return CS_EINVAL;
+  return coil_mix(c, (const float2*)in, cin, 0, cin, M, cout, (float2*)out, cout, 0, 1.0f);
+}
+
+int cs_dot(cs_ctx* c, const void* a, const void* b, double* out) {
+  if (!c || !a || !b || !out) return CS_EINVAL;
+  return vec_dot(c, (const float2*)a, (const float2*)b, c->D, out);
+}
+
+int cs_power_iteration(cs_ctx* c, const void* maps, int ncoil, int n_iter, double* L) {
+  CS_TRY(check_ready(c, maps, ncoil, maps, maps));
+  if (!L || n_iter < 0) return fail(c, CS_EINVAL, "power iteration arguments");
+  return power_iter(c, (const float2*)maps, ncoil, n_iter, L);
+}
+
+int cs_grid_shape(const cs_ctx* c, int m[3]) {
+  if (!c || !m) return CS_EINVAL;
+  m[0] = c->mz; m[1] = c->my; m[2] = c->mx;
+  return CS_OK;
+}
+
+int cs_profile_enable(cs_ctx* c, int on) {
+  if (!c) return CS_EINVAL;
+  c->prof = on != 0;
+  return CS_OK;
+}
+
+int cs_profile_read(cs_ctx* c, double* ms, long long* count) {
+  if (!c) return CS_EINVAL;
+  CS_HIP(c, hipStreamSynchronize(c->stream));
+  for (auto& r : c->prof_recs) {
+    float t = 0.f;
+    CS_HIP(c, hipEventElapsedTime(&t, r.a, r.b));
+    c->prof_ms[r.kind] += t;
+    c->prof_cnt[r.kind] += 1;
+    c->ev_pool.push_back(r.a);
+    c->ev_pool.push_back(r.b);
+  }
+  c->prof_recs.clear();
+  for (int k = 0; k < CS_NKERNELS; ++k) {
+    if (ms) ms[k] = c->prof_ms[k];
+    if (count) count[k] = c->prof_cnt[k];
+    c->prof_ms[k] = 0.0;
+    c->prof_cnt[k] = 0;
+  }
+  return CS_OK;
+}
+
+int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout,
+              cs_recon_stats* st) {
+  if (!c) return CS_EINVAL;
+  if (!c->have_op) return fail(c, CS_EINVAL, "cs_set_operator has not been called");
+  if (!y_ || !p || !x_inout) return fail(c, CS_EINVAL, "null argument");
+  if (p->mode != CS_RECON_FULL && p->mode != CS_RECON_SKETCH)
+    return fail(c, CS_EINVAL, "recon mode");
+  if (p->T < 0 || (p->mode == CS_RECON_SKETCH && p->K < 1))
+    return fail(c, CS_EINVAL, "iteration counts");
+  const float2* y = (const float2*)y_;
+  float2* x = (float2*)x_inout;
+  const long long D = c->D;
+  const int C = c->C;
+  float2* b = c->img[0];
+  float2* d = c->img[1];
+  float2* z = c->img[2];
+  float2* xt = c->img[3];
+  float2* e = c->img[4];
+  float2* g = c->img[5];
+  float2* v = c->img[6];
+  float2* xn = c->img[7];
+  if (!p->reuse_b || !c->have_b) {
+    CS_TRY(chunk_loop(c, C, op_adjoint, c->maps, y, b));
+    c->have_b = true;
+  }
+  const int Ch = p->V + p->S;
+  const int n_pow = p->n_pow > 0 ? p->n_pow : 30;
+  long long nfull = 0, nsk = 0, nprox = 0;
+  double alpha = p->step;
+  if (p->mode == CS_RECON_SKETCH) {
+    CS_TRY(sketch_impl(c, y, p->V, p->S, p->seed, p->t0, 0, c->smaps, nullptr));
+    if (alpha <= 0) {
+      double L = 0;
+      CS_TRY(power_iter(c, c->smaps, Ch, n_pow, &L));
+      nsk += n_pow + 1;
+      alpha = 1.0 / L;
+    }
+  } else if (alpha <= 0) {
+    double L = 0;
+    CS_TRY(power_iter(c, c->maps, C, n_pow, &L));
+    nfull += n_pow + 1;
+    alpha = 1.0 / L;
+  }
+  const float a = (float)alpha;
+  const float tau_l = (float)(alpha * p->lam);
+  std::vector<hipEvent_t> ev;
+  hipEvent_t ev0 = nullptr, ev_end = nullptr;
+  CS_HIP(c, hipEventCreate(&ev0));
+  CS_HIP(c, hipEventCreate(&ev_end));
+  ev.resize(std::max(1, p->T));
+  for (auto& q : ev) CS_HIP(c, hipEventCreate(&q));
+  std::vector<hipEvent_t> evd(ev.size());
+  for (auto& q : evd) CS_HIP(c, hipEventCreate(&q));
+  const bool track = p->x_ref != nullptr;
+  std::vector<double> dist_num(p->T, 0.0), dist_den(p->T, 1.0);
+  // phase timing: events around each full / sketched normal apply, prox and
+  // sketch formation
+  struct Phase {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Phase> phases;
+  auto timed = [&](int kind, auto&& fn) -> int {
+    Phase ph{kind, pool_event(c), pool_event(c)};
+    if (!ph.a || !ph.b) return fail(c, CS_EHIP, "event creation failed");
+    CS_HIP(c, hipEventRecord(ph.a, c->stream));
+    const int r = fn();
+    CS_HIP(c, hipEventRecord(ph.b, c->stream));
+    phases.push_back(ph);
+    return r;
+  };
+  CS_HIP(c, hipEventRecord(ev0, c->stream));
+  int rc = CS_OK;
+  auto record = [&](int it) -> int {
+    CS_HIP(c, hipEventRecord(ev[it], c->stream));
+    if (track) {
+      double num = 0, den = 0;
+      CS_TRY(vec_dist(c, x, (const float2*)p->x_ref, D, &num, &den));
+      dist_num[it] = num;
+      dist_den[it] = den;
+    }
+    CS_HIP(c, hipEventRecord(evd[it], c->stream));
+    return CS_OK;
+  };
+  if (p->mode == CS_RECON_FULL) {
+    // plain FISTA: g = A^H A z - b
+    CS_TRY(vec_copy(c, z, x, D));
+    double tau = 1.0;
+    for (int it = 0; it < p->T && rc == CS_OK; ++it) {
+      CS_TRY(timed(0, [&] { return op_normal(c, c->maps, C, z, g); }));
+      ++nfull;
+      CS_TRY(vec_fista_step(c, v, z, a, g, -1.f, b, D));
+      CS_TRY(timed(2, [&] { return prox_l1(c, v, tau_l, xn); }));
+      ++nprox;
+      const double tn = (1.0 + std::sqrt(1.0 + 4.0 * tau * tau)) / 2.0;
+      const float beta = (float)((tau - 1.0) / tn);
+      tau = tn;
+      CS_TRY(vec_momentum(c, z, x, xn, beta, D));
+      CS_TRY(record(it));
+    }
+  } else {
+    for (int it = 0; it < p->T; ++it) {
+      const int t = p->t0 + it;
+      // true gradient d = A^H (A x^t - y) = A^H A x^t - b (Alg. 1 line 9)
+      CS_TRY(timed(0, [&] { return op_normal(c, c->maps, C, x, g); }));
+      ++nfull;
+      CS_TRY(vec_axpby(c, d, 1.f, g, -1.f, b, D));
+      // sketched model A_S^t (Alg. 1 line 10)
+      if (it > 0)
+        CS_TRY(timed(3, [&] {
+          return sketch_impl(c, y, p->V, p->S, p->seed, t, 0, c->smaps, nullptr);
+        }));
+      // K FISTA steps on 1/2||A_S(x - x^t)||^2 + <x, d> + g(x), momentum restarted
+      CS_TRY(vec_copy(c, xt, x, D));
+      CS_TRY(vec_copy(c, z, x, D));
+      double tau = 1.0;
+      for (int k = 0; k < p->K; ++k) {
+        CS_TRY(vec_axpby(c, e, 1.f, z, -1.f, xt, D));
+        CS_TRY(timed(1, [&] { return op_normal(c, c->smaps, Ch, e, g); }));
+        ++nsk;
+        CS_TRY(vec_fista_step(c, v, z, a, g, 1.f, d, D));
+        CS_TRY(timed(2, [&] { return prox_l1(c, v, tau_l, xn); }));
+        ++nprox;
+        const double tn = (1.0 + std::sqrt(1.0 + 4.0 * tau * tau)) / 2.0;
+        const float beta = (float)((tau - 1.0) / tn);
+        tau = tn;
+        CS_TRY(vec_momentum(c, z, x, xn, beta, D));
+      }
+      CS_TRY(record(it));
+    }
+  }
+  CS_HIP(c, hipEventRecord(ev_end, c->stream));
+  CS_HIP(c, hipEventSynchronize(ev_end));
+  double excluded = 0.0;
+  for (int it = 0; it < p->T; ++it) {
+    float ms = 0.f, md = 0.f;
+    CS_HIP(c, hipEventElapsedTime(&ms, ev0, ev[it]));
+    if (st && st->time_ms) st->time_ms[it] = ms - excluded;
+    CS_HIP(c, hipEventElapsedTime(&md, ev[it], evd[it]));
+    excluded += md;
+    if (st && st->dist && track)
+      st->dist[it] = std::sqrt(dist_num[it]) / std::sqrt(dist_den[it]);
+  }
+  float total = 0.f;
+  CS_HIP(c, hipEventElapsedTime(&total, ev0, ev_end));
+  for (auto& q : ev) (void)hipEventDestroy(q);
+  for (auto& q : evd) (void)hipEventDestroy(q);
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev_end);
+  if (st) {
+    st->alpha = alpha;
+    st->n_full_applies = nfull;
+    st->n_sketch_applies = nsk;
+    st->n_prox = nprox;
+    st->total_ms = total - excluded;
+    double pms[4] = {0, 0, 0, 0};
+    for (auto& ph : phases) {
+      float ms = 0.f;
+      CS_HIP(c, hipEventElapsedTime(&ms, ph.a, ph.b));
+      pms[ph.kind] += ms;
+    }
+    st->ms_full_normal = pms[0];
+    st->ms_sketch_normal = pms[1];
+    st->ms_prox = pms[2];
+    st->ms_sketch = pms[3];
+  }
+  for (auto& ph : phases) {
+    c->ev_pool.push_back(ph.a);
+    c->ev_pool.push_back(ph.b);
+  }
+  double chk[2];
+  CS_TRY(vec_dot(c, x, x, D, chk));
+  if (!std::isfinite(chk[0])) return fail(c, CS_ENUMERIC, "reconstruction produced NaN/Inf");
+  return CS_OK;
+}
+
+}  // extern "C"

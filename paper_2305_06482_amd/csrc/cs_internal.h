@@ -1,0 +1,230 @@
+// Internal declarations of the coil-sketching HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/coilsketch.h"
+
+namespace cs {
+
+constexpr int kCoilChunk = 16;      // coils per pass of the gridding pipeline
+constexpr int kMaxFFT = 1024;       // longest axis handled by one LDS panel
+constexpr int kMaxRadices = 12;
+
+// -------------------------------------------------------------------------
+// One batched, strided 1D FFT pass over an LDS panel.
+//
+// The array is viewed as [outer][row][column]; a work-group owns one outer
+// index and Wt consecutive columns, loads the n_in rows into LDS (zero
+// filling the others when the axis is zero-padded), runs the mixed-radix
+// Stockham FFT along the rows, optionally multiplies by a sampling mask (and
+// transforms back), and stores n_out rows.  Columns index (pixel p, coil c)
+// pairs as p * cb + c; a buffer with coil leading dimension ldc and coil
+// offset c0 keeps element (p, c) at p * ldc + c0 + c.
+// -------------------------------------------------------------------------
+enum { PRO_GRID = 0, PRO_IMAGE = 1 };
+enum { EPI_GRID = 0, EPI_IMAGE = 1 };
+enum { MID_NONE = 0, MID_MASK_IFFT = 1, MID_MASK = 2 };
+
+struct PassArgs {
+  int L;                 // FFT length
+  int n_in, n_out;       // rows loaded / stored
+  int pad_in, pad_out;   // 1: image row t <-> FFT row (t - n/2) mod L
+  int dir;               // -1 forward (e^{-i}), +1 inverse (unnormalised)
+  int nrad;
+  int rad[kMaxRadices];
+  const float2* tw;      // [L] e^{-2 pi i k / L}
+  int Wt;                // panel width (columns per work-group)
+  long long nblk;        // column blocks per outer index
+  long long inner;       // columns per outer index
+  int cb;                // coils per pixel in the column space
+  // grid source / destination
+  const float2* src; long long src_os, src_rs; int src_ldc, src_c0;
+  float2* dst; long long dst_os, dst_rs; int dst_ldc, dst_c0;
+  // masks (uint8): value at outer * mask_os + row * mask_rs
+  int mid; int premask;
+  const uint8_t* mask; long long mask_os, mask_rs;
+  // image prologue / epilogue: pixel (t, p) at t * P + p
+  int prologue, epilogue, accumulate;
+  const float2* img; float2* img_out; long long P;
+  const float2* maps; int maps_ldc, maps_c0;
+  const float* da;       // [n] per-row scale along the pass axis
+  const float* dp;       // [P] per-pixel scale of the other axes
+};
+
+// Sample record of the sorted non-Cartesian trajectory (80 bytes).
+struct SampleRec {
+  int bx, by, bz;        // first tap index per axis, wrapped into [0, m)
+  int orig;              // index of the sample in the caller's order
+  float w, sw;           // density compensation w and sqrt(w)
+  float pad0, pad1;
+  float wx[4], wy[4], wz[4];
+};
+
+struct FFTPlan {
+  int L = 0;
+  int nrad = 0;
+  int rad[kMaxRadices] = {0};
+  float2* tw = nullptr;  // device
+};
+
+}  // namespace cs
+
+struct cs_ctx {
+  cs_geom g{};
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // normalised 3D geometry (2D: nz = mz = 1)
+  int ndim = 2;
+  int nz = 1, ny = 1, nx = 1;
+  int mz = 1, my = 1, mx = 1;
+  long long D = 0, M = 0, N = 0;
+  int C = 0;
+  float beta = 0.f;
+
+  std::map<int, cs::FFTPlan> plans;
+
+  // operator
+  const float2* maps = nullptr;   // borrowed [D][C]
+  bool have_op = false;
+  uint8_t* mask = nullptr;        // Cartesian [D]
+  bool mask1d = false;            // mask constant along x: only y-FFTs needed
+  float* da[3] = {nullptr, nullptr, nullptr};  // per-axis scale tables
+  float* dp_z = nullptr;          // [ny*nx] per-pixel table for a z pass
+  float* dp_y = nullptr;          // [nx] per-pixel table for a y pass (2D)
+  float* da_y1d = nullptr;        // [ny] 1/sqrt(ny): unitary y-only FFT pair
+  float* ones = nullptr;          // [max(n)] ones
+
+  // non-Cartesian
+  cs::SampleRec* rec = nullptr;   // [N] sorted
+  float* dcf_orig = nullptr;      // [N] caller order (nullptr: w = 1)
+  int tile[3] = {1, 1, 1};        // tile size (tz, ty, tx)
+  int ntile[3] = {1, 1, 1};
+  long long ntiles = 0;
+  int* tile_off = nullptr;        // [ntiles + 1]
+  int* tile_list = nullptr;
+
+  // work buffers
+  float2* gridA = nullptr;        // M * kCoilChunk
+  float2* gridB = nullptr;
+  float2* vbuf = nullptr;         // N * kCoilChunk (non-Cartesian)
+  std::vector<float2*> img;       // D-sized scratch images
+  double* red = nullptr;          // reduction partials
+  double* red_out = nullptr;      // final reduction values (device)
+  double* host_red = nullptr;     // pinned host copy
+
+  // sketch cache
+  bool have_U = false;
+  std::vector<double> U;          // C*C complex (re, im) row-major
+  std::vector<double> lam;
+  float2* vmaps = nullptr;        // [D][C] virtual maps U^H c
+  double* cov_part = nullptr;     // covariance partials
+  double* cov = nullptr;          // [C][C] complex double
+  double* eig_dev = nullptr;      // U and lambda from the eigensolver
+  void* mixB = nullptr;           // packed bf16 B fragments for coil mixing
+  size_t mixB_bytes = 0;
+
+  // wavelet work
+  float2* wav1 = nullptr;
+  float2* wav2 = nullptr;
+
+  // recon
+  bool have_b = false;
+  float2* smaps = nullptr;        // [D][C] sketched maps of the current t
+
+  // per-kernel event timing
+  struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  bool prof = false;
+  std::vector<ProfRec> prof_recs;
+  std::vector<hipEvent_t> ev_pool;
+  double prof_ms[CS_NKERNELS] = {0};
+  long long prof_cnt[CS_NKERNELS] = {0};
+};
+
+namespace cs {
+
+// error helpers
+int fail(cs_ctx* c, int code, const std::string& msg);
+#define CS_HIP(ctx, expr)                                                   \
+  do {                                                                      \
+    hipError_t _e = (expr);                                                 \
+    if (_e != hipSuccess)                                                   \
+      return ::cs::fail((ctx), CS_EHIP,                                     \
+                        std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+#define CS_TRY(expr)            \
+  do {                          \
+    int _r = (expr);            \
+    if (_r != CS_OK) return _r; \
+  } while (0)
+
+// kernel kinds for event timing (see cs_profile_read)
+enum {
+  K_PASS = 0, K_INTERP, K_SPREAD, K_GATHER, K_WAVELET, K_SOFT, K_VEC, K_REDUCE,
+  K_COV, K_EIG, K_MIX
+};
+void prof_begin(cs_ctx* c, int kind);
+void prof_end(cs_ctx* c);
+#define CS_KLAUNCH(ctx, kind, ...)     \
+  do {                                 \
+    ::cs::prof_begin((ctx), (kind));   \
+    hipLaunchKernelGGL(__VA_ARGS__);   \
+    ::cs::prof_end((ctx));             \
+  } while (0)
+
+// fft_pass.hip
+int get_plan(cs_ctx* c, int L, const FFTPlan** out);
+int launch_pass(cs_ctx* c, PassArgs& a, long long n_outer);
+void fill_plan(PassArgs& a, const FFTPlan* p);
+
+// grid.hip
+int setup_noncart(cs_ctx* c, const float* coords, const float* dcf);
+int launch_interp(cs_ctx* c, const float2* grid, int cb, int weight_mode,
+                  float2* out, int out_ldc, int out_c0, int caller_order);
+int launch_spread(cs_ctx* c, const float2* vals, int cb, float2* grid);
+int launch_gather_samples(cs_ctx* c, const float2* y, int ldc, int c0, int cb,
+                          float2* vals);
+enum { W_NONE = 0, W_SQRT = 1, W_FULL = 2 };
+double kb_i0(double x);
+double kb_ft(double nu, double W, double beta);
+
+// vec.hip
+int vec_fill(cs_ctx* c, float2* x, long long n, float re, float im);
+int vec_axpby(cs_ctx* c, float2* out, float a, const float2* x, float b,
+              const float2* y, long long n);
+int vec_copy(cs_ctx* c, float2* out, const float2* x, long long n);
+int vec_dot(cs_ctx* c, const float2* a, const float2* b, long long n,
+            double out[2]);
+int vec_fista_step(cs_ctx* c, float2* v, const float2* z, float alpha,
+                   const float2* g1, float s2, const float2* g2, long long n);
+int vec_momentum(cs_ctx* c, float2* z, float2* x, const float2* xn, float beta,
+                 long long n);
+int vec_dist(cs_ctx* c, const float2* a, const float2* b, long long n,
+             double* num, double* den);
+
+// wavelet.hip
+int wavelet_init(cs_ctx* c);
+int dwt_fwd(cs_ctx* c, const float2* x, float2* coef);
+int dwt_inv(cs_ctx* c, const float2* coef, float2* x);
+int prox_l1(cs_ctx* c, const float2* v, float tau, float2* out);
+
+// sketch.hip
+int covariance_eig(cs_ctx* c, const float2* y);
+int coil_mix(cs_ctx* c, const float2* in, int in_ldc, int in_c0, int cin,
+             const double* M, int cout, float2* out, int out_ldc, int out_c0,
+             float out_scale);
+
+// operators (api.cpp)
+int op_normal(cs_ctx* c, const float2* maps, int ncoil, const float2* x,
+              float2* out);
+
+}  // namespace cs

@@ -1,0 +1,299 @@
+// Batched mixed-radix FFT passes over LDS panels, with the sensitivity
+// multiply / deapodisation / zero-padding fused into the first pass and the
+// conjugate-map coil reduction fused into the last one (Sec. 2.1, Eqs. 2 and
+// 5; Eq. 12 for the sketched maps).
+//
+// The FFT is a Stockham autosort transform: for radix R and current span Ns,
+// butterfly j reads rows j + r L/R, multiplies element r by the twiddle
+// e^{-2 pi i (j mod Ns) r / (Ns R)}, takes the R-point DFT and writes rows
+// (j / Ns) Ns R + (j mod Ns) + r Ns.  Radices 2, 3, 4 and 5 cover every
+// length of the form 2^a 3^b 5^c.
+#include <cmath>
+
+#include "cs_internal.h"
+
+namespace cs {
+
+namespace {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // conj(a) * b
+  return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) {
+  return make_float2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ float2 csub(float2 a, float2 b) {
+  return make_float2(a.x - b.x, a.y - b.y);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) {
+  return make_float2(a.x * s, a.y * s);
+}
+// multiply by -i (dir < 0) or +i (dir > 0)
+__device__ __forceinline__ float2 mul_i(float2 a, int dir) {
+  return dir < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+}
+
+// cos / sin of 2 pi / 3 and 2 pi / 5, 4 pi / 5
+constexpr float kS3 = 0.86602540378443864676f;
+constexpr float kC51 = 0.30901699437494742410f;
+constexpr float kC52 = -0.80901699437494742410f;
+constexpr float kS51 = 0.95105651629515357212f;
+constexpr float kS52 = 0.58778525229247312917f;
+
+__device__ __forceinline__ void dft2(float2* v) {
+  float2 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+__device__ __forceinline__ void dft3(float2* v, int dir) {
+  float2 t1 = cadd(v[1], v[2]);
+  float2 t2 = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
+  float2 t3 = mul_i(cscale(csub(v[1], v[2]), kS3), dir);
+  v[0] = cadd(v[0], t1);
+  v[1] = cadd(t2, t3);
+  v[2] = csub(t2, t3);
+}
+
+__device__ __forceinline__ void dft4(float2* v, int dir) {
+  float2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+  float2 c = cadd(v[1], v[3]), d = mul_i(csub(v[1], v[3]), dir);
+  v[0] = cadd(a, c);
+  v[2] = csub(a, c);
+  v[1] = cadd(b, d);
+  v[3] = csub(b, d);
+}
+
+__device__ __forceinline__ void dft5(float2* v, int dir) {
+  float2 a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+  float2 a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+  float2 x0 = v[0];
+  float2 r1 = make_float2(x0.x + kC51 * a1.x + kC52 * a2.x, x0.y + kC51 * a1.y + kC52 * a2.y);
+  float2 r2 = make_float2(x0.x + kC52 * a1.x + kC51 * a2.x, x0.y + kC52 * a1.y + kC51 * a2.y);
+  float2 i1 = mul_i(make_float2(kS51 * b1.x + kS52 * b2.x, kS51 * b1.y + kS52 * b2.y), dir);
+  float2 i2 = mul_i(make_float2(kS52 * b1.x - kS51 * b2.x, kS52 * b1.y - kS51 * b2.y), dir);
+  v[0] = make_float2(x0.x + a1.x + a2.x, x0.y + a1.y + a2.y);
+  v[1] = cadd(r1, i1);
+  v[4] = csub(r1, i1);
+  v[2] = cadd(r2, i2);
+  v[3] = csub(r2, i2);
+}
+
+// Stockham FFT of Wt columns of length L held in LDS (row-major [L][Wt]).
+// Returns the buffer that holds the result.
+__device__ float2* fft_lds(float2* b0, float2* b1, const float2* tw, int L, int Wt,
+                           int dir, const int* rad, int nrad) {
+  int Ns = 1;
+  for (int s = 0; s < nrad; ++s) {
+    const int R = rad[s];
+    const int nbf = L / R;
+    const int tstep = L / (Ns * R);
+    const int total = nbf * Wt;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+      const int col = idx % Wt;
+      const int j = idx / Wt;
+      const int k = j % Ns;
+      float2 v[5];
+#pragma unroll
+      for (int r = 0; r < 5; ++r)
+        if (r < R) v[r] = b0[(j + r * nbf) * Wt + col];
+#pragma unroll
+      for (int r = 1; r < 5; ++r) {
+        if (r < R) {
+          float2 w = tw[k * r * tstep];
+          if (dir > 0) w.y = -w.y;
+          v[r] = cmul(v[r], w);
+        }
+      }
+      switch (R) {
+        case 2: dft2(v); break;
+        case 3: dft3(v, dir); break;
+        case 4: dft4(v, dir); break;
+        default: dft5(v, dir); break;
+      }
+      const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+      for (int r = 0; r < 5; ++r)
+        if (r < R) b1[(base + r * Ns) * Wt + col] = v[r];
+    }
+    __syncthreads();
+    float2* t = b0;
+    b0 = b1;
+    b1 = t;
+    Ns *= R;
+  }
+  return b0;
+}
+
+__device__ __forceinline__ int wrap_row(int t, int n, int L) {
+  int r = t - n / 2;
+  return r < 0 ? r + L : r;
+}
+
+__global__ __launch_bounds__(256) void k_axis_pass(PassArgs a) {
+  extern __shared__ float2 smem[];
+  const int L = a.L, Wt = a.Wt;
+  float2* b0 = smem;
+  float2* b1 = smem + (size_t)L * Wt;
+  float2* tw = smem + (size_t)2 * L * Wt;
+  __shared__ int rad[kMaxRadices];
+  const long long blk = blockIdx.x;
+  const long long outer = blk / a.nblk;
+  const long long col0 = (blk - outer * a.nblk) * Wt;
+  const int ncol = (int)min((long long)Wt, a.inner - col0);
+  const int tid = threadIdx.x, bd = blockDim.x;
+
+  if (tid < kMaxRadices) rad[tid] = a.rad[tid];
+  for (int i = tid; i < L; i += bd) tw[i] = a.tw[i];
+  if (a.n_in < L || ncol < Wt)
+    for (int i = tid; i < L * Wt; i += bd) b0[i] = make_float2(0.f, 0.f);
+  __syncthreads();
+
+  // ---- load ---------------------------------------------------------------
+  for (int idx = tid; idx < a.n_in * Wt; idx += bd) {
+    const int t = idx / Wt, col = idx % Wt;
+    if (col >= ncol) continue;
+    const long long ci = col0 + col;
+    const long long p = ci / a.cb;
+    const int c = (int)(ci - p * a.cb);
+    float2 v;
+    if (a.prologue == PRO_IMAGE) {
+      const long long pix = (long long)t * a.P + p;
+      const float2 xv = a.img[pix];
+      const float2 m = a.maps[pix * a.maps_ldc + a.maps_c0 + c];
+      v = cscale(cmul(xv, m), a.da[t] * a.dp[p]);
+    } else {
+      v = a.src[outer * a.src_os + (long long)t * a.src_rs + p * a.src_ldc + a.src_c0 + c];
+    }
+    if (a.premask && a.mask[outer * a.mask_os + (long long)t * a.mask_rs] == 0)
+      v = make_float2(0.f, 0.f);
+    const int row = a.pad_in ? wrap_row(t, a.n_in, L) : t;
+    b0[row * Wt + col] = v;
+  }
+  __syncthreads();
+
+  float2* r = fft_lds(b0, b1, tw, L, Wt, a.dir, rad, a.nrad);
+
+  if (a.mid != MID_NONE) {
+    for (int idx = tid; idx < L * Wt; idx += bd) {
+      const int row = idx / Wt;
+      if (a.mask[outer * a.mask_os + (long long)row * a.mask_rs] == 0)
+        r[idx] = make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    if (a.mid == MID_MASK_IFFT) {
+      float2* other = (r == b0) ? b1 : b0;
+      r = fft_lds(r, other, tw, L, Wt, -a.dir, rad, a.nrad);
+    }
+  }
+
+  // ---- store --------------------------------------------------------------
+  if (a.epilogue == EPI_IMAGE) {
+    const int npix = ncol / a.cb;
+    const long long p0 = col0 / a.cb;
+    for (int idx = tid; idx < a.n_out * npix; idx += bd) {
+      const int t = idx / npix, pl = idx % npix;
+      const int row = a.pad_out ? wrap_row(t, a.n_out, L) : t;
+      const long long p = p0 + pl;
+      const long long pix = (long long)t * a.P + p;
+      const float2* mp = a.maps + pix * a.maps_ldc + a.maps_c0;
+      const float2* rv = r + row * Wt + pl * a.cb;
+      float2 acc = make_float2(0.f, 0.f);
+      for (int c = 0; c < a.cb; ++c) acc = cadd(acc, cmulc(mp[c], rv[c]));
+      acc = cscale(acc, a.da[t] * a.dp[p]);
+      if (a.accumulate) acc = cadd(acc, a.img_out[pix]);
+      a.img_out[pix] = acc;
+    }
+  } else {
+    for (int idx = tid; idx < a.n_out * Wt; idx += bd) {
+      const int t = idx / Wt, col = idx % Wt;
+      if (col >= ncol) continue;
+      const int row = a.pad_out ? wrap_row(t, a.n_out, L) : t;
+      const long long ci = col0 + col;
+      const long long p = ci / a.cb;
+      const int c = (int)(ci - p * a.cb);
+      a.dst[outer * a.dst_os + (long long)t * a.dst_rs + p * a.dst_ldc + a.dst_c0 + c] =
+          r[row * Wt + col];
+    }
+  }
+}
+
+bool factorize(int L, int* rad, int* nrad) {
+  int n = L, k = 0;
+  while (n % 4 == 0 && k < kMaxRadices) { rad[k++] = 4; n /= 4; }
+  while (n % 2 == 0 && k < kMaxRadices) { rad[k++] = 2; n /= 2; }
+  while (n % 3 == 0 && k < kMaxRadices) { rad[k++] = 3; n /= 3; }
+  while (n % 5 == 0 && k < kMaxRadices) { rad[k++] = 5; n /= 5; }
+  *nrad = k;
+  return n == 1;
+}
+
+}  // namespace
+
+int get_plan(cs_ctx* c, int L, const FFTPlan** out) {
+  auto it = c->plans.find(L);
+  if (it != c->plans.end()) {
+    *out = &it->second;
+    return CS_OK;
+  }
+  if (L < 1 || L > kMaxFFT)
+    return fail(c, CS_EINVAL, "FFT length " + std::to_string(L) + " out of range");
+  FFTPlan p;
+  p.L = L;
+  if (!factorize(L, p.rad, &p.nrad))
+    return fail(c, CS_EINVAL, "FFT length " + std::to_string(L) +
+                                  " has a prime factor other than 2, 3, 5");
+  std::vector<float2> tw(L);
+  for (int k = 0; k < L; ++k) {
+    const double ang = -2.0 * M_PI * (double)k / (double)L;
+    tw[k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+  }
+  CS_HIP(c, hipMalloc(&p.tw, sizeof(float2) * L));
+  CS_HIP(c, hipMemcpy(p.tw, tw.data(), sizeof(float2) * L, hipMemcpyHostToDevice));
+  c->plans[L] = p;
+  *out = &c->plans[L];
+  return CS_OK;
+}
+
+void fill_plan(PassArgs& a, const FFTPlan* p) {
+  a.L = p->L;
+  a.nrad = p->nrad;
+  for (int i = 0; i < kMaxRadices; ++i) a.rad[i] = p->rad[i];
+  a.tw = p->tw;
+}
+
+int launch_pass(cs_ctx* c, PassArgs& a, long long n_outer) {
+  const int L = a.L;
+  const bool image_cols = (a.prologue == PRO_IMAGE || a.epilogue == EPI_IMAGE);
+  // panel width: as many columns as fit a 64 KiB LDS budget, a multiple of
+  // cb when the columns are (pixel, coil) pairs of an image pass
+  const long long budget = 64 * 1024 / sizeof(float2);
+  long long w = (budget - L) / (2LL * L);
+  if (image_cols) w = (w / a.cb) * a.cb;
+  if (w < (image_cols ? a.cb : 1)) w = image_cols ? a.cb : 1;
+  if (w > a.inner) w = a.inner;
+  if (image_cols && (a.inner % a.cb) != 0)
+    return fail(c, CS_EINVAL, "image pass columns not a multiple of the coil count");
+  a.Wt = (int)w;
+  const size_t lds = sizeof(float2) * ((size_t)2 * L * a.Wt + L);
+  if (lds > 160 * 1024)
+    return fail(c, CS_EINVAL, "FFT panel does not fit in LDS");
+  if (a.n_in > L || a.n_out > L)
+    return fail(c, CS_EINVAL, "pass rows exceed FFT length");
+  const long long nblk = (a.inner + a.Wt - 1) / a.Wt;
+  a.nblk = nblk;
+  if (nblk * n_outer > 0x7fffffffLL || n_outer < 1)
+    return fail(c, CS_EINVAL, "pass grid too large");
+  dim3 grid((unsigned)(nblk * n_outer));
+  if (lds > 64 * 1024)
+    CS_HIP(c, hipFuncSetAttribute((const void*)k_axis_pass,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  CS_KLAUNCH(c, K_PASS, k_axis_pass, grid, dim3(256), lds, c->stream, a);
+  CS_HIP(c, hipGetLastError());
+  return CS_OK;
+}
+
+}  // namespace cs

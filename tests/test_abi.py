@@ -1,0 +1,60 @@
+"""The C-ABI library loads and exports every symbol the header declares
+(no compute: runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HDR = os.path.join(ROOT, "include", "coilsketch.h")
+LIB = os.path.join(ROOT, "paper_2305_06482_amd", "libcoilsketch.so")
+
+
+def declared():
+    txt = open(HDR).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:int|void|const char\s*\*)\s+(\w+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for n in ["cs_create", "cs_destroy", "cs_last_error", "cs_set_operator", "sense_apply",
+              "sense_adjoint", "normal_apply", "sketch_build", "recon_run"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    lib = ctypes.CDLL(LIB)
+    for n in declared():
+        assert hasattr(lib, n), n
+
+
+def test_binding_lists_every_symbol():
+    from paper_2305_06482_amd import binding
+    assert sorted(binding.EXPORTED) == declared()
+
+
+def test_create_rejects_bad_geometry_without_gpu():
+    # argument validation happens before any device call
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    from paper_2305_06482_amd import binding
+    lib = binding.load()
+    g = binding.Geom()
+    g.ndim = 5
+    out = ctypes.c_void_p()
+    assert lib.cs_create(ctypes.byref(g), None, ctypes.byref(out)) == -1
+    assert b"ndim" in lib.cs_last_error(None)
+    g.ndim = 3
+    g.n[0], g.n[1], g.n[2] = 16, 16, 16
+    g.ncoil = 4
+    g.kind = binding.CS_CART
+    assert lib.cs_create(ctypes.byref(g), None, ctypes.byref(out)) == -2
+    g.kind = binding.CS_NONCART
+    g.kwidth = 6
+    g.sigma = 1.25
+    assert lib.cs_create(ctypes.byref(g), None, ctypes.byref(out)) == -2
