@@ -554,6 +554,7 @@ void cs_destroy(cs_ctx* c) {
   fr(c->cov_part); fr(c->cov); fr(c->eig_dev); fr(c->vmaps); fr(c->smaps);
   fr(c->wav1); fr(c->wav2); fr(c->mask); fr(c->rec); fr(c->dcf_orig);
   fr(c->tile_off); fr(c->tile_list); fr(c->mixB); fr(c->ones);
+  fr(c->items); fr(c->merges); fr(c->partial);
   for (int a = 0; a < 3; ++a) fr(c->da[a]);
   fr(c->dp_z); fr(c->dp_y); fr(c->da_y1d);
   for (auto* p : c->img) fr(p);
@@ -600,6 +601,10 @@ int cs_set_operator(cs_ctx* c, const void* maps, const uint8_t* mask, const floa
       CS_HIP(c, hipFree(c->rec)); c->rec = nullptr;
       CS_HIP(c, hipFree(c->tile_off)); c->tile_off = nullptr;
       CS_HIP(c, hipFree(c->tile_list)); c->tile_list = nullptr;
+      CS_HIP(c, hipFree(c->items)); c->items = nullptr;
+      CS_HIP(c, hipFree(c->merges)); c->merges = nullptr;
+      CS_HIP(c, hipFree(c->partial)); c->partial = nullptr;
+      c->n_items = c->n_merges = 0;
     }
     if (c->dcf_orig) {
       CS_HIP(c, hipFree(c->dcf_orig));

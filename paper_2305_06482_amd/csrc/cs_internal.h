@@ -109,6 +109,12 @@ struct cs_ctx {
   long long ntiles = 0;
   int* tile_off = nullptr;        // [ntiles + 1]
   int* tile_list = nullptr;
+  int4* items = nullptr;          // spread work items (tile, kbeg, kend, slot)
+  long long n_items = 0;
+  int4* merges = nullptr;         // split tiles (tile, first slot, slots, 0)
+  long long n_merges = 0;
+  float2* partial = nullptr;      // partial tiles of split tiles
+  int spread_nw = 4;              // waves per spread work-group
 
   // work buffers
   float2* gridA = nullptr;        // M * kCoilChunk

@@ -221,6 +221,195 @@ __global__ __launch_bounds__(256) void k_axis_pass(PassArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Specialised pass for a compile-time length L and column-group width TC:
+// thread (tr, tc) owns column tc of the panel and butterflies tr, tr + TR, ...
+// of every stage; each stage reads its inputs into registers, synchronises,
+// and writes the outputs back in place, so one LDS buffer suffices and all
+// index arithmetic of the stages is resolved at compile time.
+// ---------------------------------------------------------------------------
+struct RadPlan {
+  int n;
+  int r[kMaxRadices];
+};
+
+constexpr RadPlan make_radplan(int L) {
+  RadPlan p{0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
+  while (L % 4 == 0) { p.r[p.n++] = 4; L /= 4; }
+  while (L % 2 == 0) { p.r[p.n++] = 2; L /= 2; }
+  while (L % 3 == 0) { p.r[p.n++] = 3; L /= 3; }
+  while (L % 5 == 0) { p.r[p.n++] = 5; L /= 5; }
+  return p;
+}
+
+template <int R>
+__device__ __forceinline__ void dftR(float2* v, int dir) {
+  if constexpr (R == 2) dft2(v);
+  else if constexpr (R == 3) dft3(v, dir);
+  else if constexpr (R == 4) dft4(v, dir);
+  else dft5(v, dir);
+}
+
+template <int L, int TC, int R, int NS>
+__device__ __forceinline__ void fft_stage(float2* buf, const float2* tw, int tr, int tc,
+                                          int dir) {
+  constexpr int TR = 256 / TC;
+  constexpr int NBF = L / R;
+  constexpr int NB = (NBF + TR - 1) / TR;
+  constexpr int TSTEP = L / (NS * R);
+  float2 v[NB][R];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = tr + b * TR;
+    if (NB * TR == NBF || j < NBF) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = buf[(j + r * NBF) * TC + tc];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = tr + b * TR;
+    if (NB * TR == NBF || j < NBF) {
+      const int k = j % NS;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        float2 w = tw[k * r * TSTEP];
+        if (dir > 0) w.y = -w.y;
+        v[b][r] = cmul(v[b][r], w);
+      }
+      dftR<R>(v[b], dir);
+      const int base = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[(base + r * NS) * TC + tc] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int L, int TC, int S, int NS>
+__device__ __forceinline__ void fft_stages(float2* buf, const float2* tw, int tr, int tc,
+                                           int dir) {
+  constexpr RadPlan P = make_radplan(L);
+  if constexpr (S < P.n) {
+    constexpr int R = P.r[S];
+    fft_stage<L, TC, R, NS>(buf, tw, tr, tc, dir);
+    fft_stages<L, TC, S + 1, NS * R>(buf, tw, tr, tc, dir);
+  }
+}
+
+template <int L, int TC>
+__global__ __launch_bounds__(256) void k_pass_t(PassArgs a) {
+  constexpr int TR = 256 / TC;
+  extern __shared__ float2 smem[];
+  float2* buf = smem;             // [L][TC]
+  float2* tw = smem + L * TC;     // [L]
+  const int tid = threadIdx.x;
+  const int tc = tid % TC, tr = tid / TC;
+  const long long blk = blockIdx.x;
+  const long long outer = blk / a.nblk;
+  const long long col0 = (blk - outer * a.nblk) * a.Wt;
+  const int ncol = (int)min((long long)a.Wt, a.inner - col0);
+  const bool colok = tc < ncol;
+  const long long ci = col0 + tc;
+  const long long p = colok ? ci / a.cb : 0;
+  const int c = colok ? (int)(ci - p * a.cb) : 0;
+
+  for (int i = tid; i < L; i += 256) tw[i] = a.tw[i];
+  if (a.n_in < L)
+    for (int r = tr; r < L; r += TR) buf[r * TC + tc] = make_float2(0.f, 0.f);
+  __syncthreads();
+
+  if (colok) {
+    const uint8_t* mrow = a.premask ? a.mask + outer * a.mask_os : nullptr;
+    if (a.prologue == PRO_IMAGE) {
+      const float dpv = a.dp[p];
+      for (int t = tr; t < a.n_in; t += TR) {
+        const long long pix = (long long)t * a.P + p;
+        float2 v = cscale(cmul(a.img[pix], a.maps[pix * a.maps_ldc + a.maps_c0 + c]),
+                          a.da[t] * dpv);
+        if (mrow && mrow[(long long)t * a.mask_rs] == 0) v = make_float2(0.f, 0.f);
+        const int row = a.pad_in ? wrap_row(t, a.n_in, L) : t;
+        buf[row * TC + tc] = v;
+      }
+    } else {
+      const float2* src = a.src + outer * a.src_os + p * a.src_ldc + a.src_c0 + c;
+      for (int t = tr; t < a.n_in; t += TR) {
+        float2 v = src[(long long)t * a.src_rs];
+        if (mrow && mrow[(long long)t * a.mask_rs] == 0) v = make_float2(0.f, 0.f);
+        const int row = a.pad_in ? wrap_row(t, a.n_in, L) : t;
+        buf[row * TC + tc] = v;
+      }
+    }
+  }
+  __syncthreads();
+
+  fft_stages<L, TC, 0, 1>(buf, tw, tr, tc, a.dir);
+
+  if (a.mid != MID_NONE) {
+    const uint8_t* mrow = a.mask + outer * a.mask_os;
+    for (int r = tr; r < L; r += TR)
+      if (mrow[(long long)r * a.mask_rs] == 0) buf[r * TC + tc] = make_float2(0.f, 0.f);
+    __syncthreads();
+    if (a.mid == MID_MASK_IFFT) fft_stages<L, TC, 0, 1>(buf, tw, tr, tc, -a.dir);
+  }
+
+  if (a.epilogue == EPI_IMAGE) {
+    if (colok && c == 0) {
+      const float dpv = a.dp[p];
+      for (int t = tr; t < a.n_out; t += TR) {
+        const int row = a.pad_out ? wrap_row(t, a.n_out, L) : t;
+        const long long pix = (long long)t * a.P + p;
+        const float2* mp = a.maps + pix * a.maps_ldc + a.maps_c0;
+        const float2* rv = buf + row * TC + tc;
+        float2 acc = make_float2(0.f, 0.f);
+        for (int cc = 0; cc < a.cb; ++cc) acc = cadd(acc, cmulc(mp[cc], rv[cc]));
+        acc = cscale(acc, a.da[t] * dpv);
+        if (a.accumulate) acc = cadd(acc, a.img_out[pix]);
+        a.img_out[pix] = acc;
+      }
+    }
+  } else if (colok) {
+    float2* dst = a.dst + outer * a.dst_os + p * a.dst_ldc + a.dst_c0 + c;
+    for (int t = tr; t < a.n_out; t += TR) {
+      const int row = a.pad_out ? wrap_row(t, a.n_out, L) : t;
+      dst[(long long)t * a.dst_rs] = buf[row * TC + tc];
+    }
+  }
+}
+
+using PassKernel = void (*)(PassArgs);
+
+template <int L>
+PassKernel pick_tc(int TC) {
+  if (TC <= 16) return k_pass_t<L, 16>;
+  if (TC <= 32) return k_pass_t<L, 32>;
+  return k_pass_t<L, 64>;
+}
+
+PassKernel specialised(int L, int TC) {
+  switch (L) {
+    case 20: return pick_tc<20>(TC);
+    case 30: return pick_tc<30>(TC);
+    case 40: return pick_tc<40>(TC);
+    case 48: return pick_tc<48>(TC);
+    case 60: return pick_tc<60>(TC);
+    case 64: return pick_tc<64>(TC);
+    case 80: return pick_tc<80>(TC);
+    case 96: return pick_tc<96>(TC);
+    case 120: return pick_tc<120>(TC);
+    case 128: return pick_tc<128>(TC);
+    case 160: return pick_tc<160>(TC);
+    case 192: return pick_tc<192>(TC);
+    case 240: return pick_tc<240>(TC);
+    case 256: return pick_tc<256>(TC);
+    case 320: return pick_tc<320>(TC);
+    case 384: return pick_tc<384>(TC);
+    case 480: return pick_tc<480>(TC);
+    default: return nullptr;
+  }
+}
+
 bool factorize(int L, int* rad, int* nrad) {
   int n = L, k = 0;
   while (n % 4 == 0 && k < kMaxRadices) { rad[k++] = 4; n /= 4; }
@@ -268,6 +457,37 @@ void fill_plan(PassArgs& a, const FFTPlan* p) {
 int launch_pass(cs_ctx* c, PassArgs& a, long long n_outer) {
   const int L = a.L;
   const bool image_cols = (a.prologue == PRO_IMAGE || a.epilogue == EPI_IMAGE);
+  if (a.n_in > L || a.n_out > L) return fail(c, CS_EINVAL, "pass rows exceed FFT length");
+  if (image_cols && (a.inner % a.cb) != 0)
+    return fail(c, CS_EINVAL, "image pass columns not a multiple of the coil count");
+  if (specialised(L, 16) != nullptr && a.cb <= 64) {
+    // widest column group with at most 16 elements per thread (registers)
+    // whose single LDS buffer fits an 80 KiB budget
+    int tcmax = 64;
+    while (tcmax > 16 && ((long long)L * tcmax > 4096 ||
+                          sizeof(float2) * ((size_t)L * tcmax + L) > 80 * 1024))
+      tcmax /= 2;
+    long long w = tcmax;
+    if (image_cols) w = std::max<long long>(a.cb, (tcmax / a.cb) * a.cb);
+    if (w > a.inner) w = a.inner;
+    int TC = 16;
+    while (TC < w) TC *= 2;
+    if (TC <= 64) {
+      a.Wt = (int)w;
+      const long long nblk = (a.inner + a.Wt - 1) / a.Wt;
+      a.nblk = nblk;
+      if (nblk * n_outer > 0x7fffffffLL || n_outer < 1)
+        return fail(c, CS_EINVAL, "pass grid too large");
+      const size_t lds = sizeof(float2) * ((size_t)L * TC + L);
+      PassKernel k = specialised(L, TC);
+      if (lds > 64 * 1024)
+        CS_HIP(c, hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds));
+      CS_KLAUNCH(c, K_PASS, k, dim3((unsigned)(nblk * n_outer)), dim3(256), lds, c->stream, a);
+      CS_HIP(c, hipGetLastError());
+      return CS_OK;
+    }
+  }
   // panel width: as many columns as fit a 64 KiB LDS budget, a multiple of
   // cb when the columns are (pixel, coil) pairs of an image pass
   const long long budget = 64 * 1024 / sizeof(float2);
