@@ -74,6 +74,91 @@ def cpu_baseline(p, Ch, geom):
             "seconds_per_apply": per_apply}
 
 
+def first_below(dist, thr):
+    for i, d in enumerate(dist):
+        if d <= thr:
+            return i
+    return None
+
+
+def time_to_accuracy(ctx, y, p, args, log):
+    """Time to d(x^t) = ||x^t - x_inf|| / ||x_inf|| <= thr (Sec. 3.3.1) for the
+    plain full-coil FISTA and for Algorithm 1, both in FP32 on this GPU.
+
+    x_inf is the full-coil problem's minimizer, found by plain FISTA run in
+    chunks (momentum restarted per chunk) until one chunk changes x by less
+    than 1e-5 relative.  Times are GPU event times on the context stream:
+    `loop_ms` covers the iterations up to the first one within thr, `prep_ms`
+    the set-up (b = A^H y, step size by power iteration, PCA basis and first
+    sketch)."""
+    import torch
+    thr = args.tta_thr
+    C, V, S = p.n_coils, p.V, p.S
+    dev = y.device
+    t0 = time.time()
+    pf = ctx.recon_run(y, mode="full", lam=p.lam, T=0, step=0.0, n_pow=30)
+    alpha_f = pf.alpha
+    x_inf = torch.zeros(p.shape, dtype=torch.complex64, device=dev)
+    change, its = None, 0
+    while its < args.tta_ref_iters:
+        prev = x_inf.clone()
+        ctx.recon_run(y, mode="full", lam=p.lam, T=args.tta_chunk, step=alpha_f,
+                      reuse_b=True, x=x_inf)
+        its += args.tta_chunk
+        change = (torch.linalg.vector_norm(x_inf - prev) /
+                  torch.linalg.vector_norm(x_inf)).item()
+        log(f"x_inf: {its} full FISTA iterations, last-chunk change {change:.3e}")
+        if change < 1e-5:
+            break
+    ref = {"iterations": its, "chunk": args.tta_chunk, "last_chunk_rel_change": change,
+           "wall_s": round(time.time() - t0, 1)}
+
+    def summarize(r, n_full_per_it, n_sk_per_it, pre_full, pre_sk):
+        i = first_below(r.dist, thr)
+        out = {"prep_ms": r.prep_ms, "iterations_run": len(r.dist),
+               "final_dist": r.dist[-1] if r.dist else None, "alpha": r.alpha}
+        if i is None:
+            out.update({"converged": False})
+            return out
+        out.update({
+            "converged": True, "iterations": i + 1,
+            "loop_ms": r.time_ms[i], "total_ms": r.time_ms[i] + r.prep_ms,
+            "full_applies": pre_full + (i + 1) * n_full_per_it,
+            "sketched_applies": pre_sk + (i + 1) * n_sk_per_it,
+        })
+        out["coil_ffts"] = 2 * (out["full_applies"] * C + out["sketched_applies"] * (V + S))
+        return out
+
+    x = torch.zeros(p.shape, dtype=torch.complex64, device=dev)
+    rf = ctx.recon_run(y, mode="full", lam=p.lam, T=args.tta_full_iters, step=0.0, n_pow=30,
+                       reuse_b=False, x=x, x_ref=x_inf)
+    full = summarize(rf, 1, 0, 31, 0)
+    log(f"full-coil FISTA: {full}")
+
+    # PCA basis recomputed so that its cost is part of the sketched set-up
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    ctx.sketch_build(y, V, S, p.seed, 1, refresh=True, host_outputs=False)
+    ev[1].record()
+    torch.cuda.synchronize()
+    pca_ms = ev[0].elapsed_time(ev[1])
+    x = torch.zeros(p.shape, dtype=torch.complex64, device=dev)
+    rs = ctx.recon_run(y, mode="sketch", lam=p.lam, T=args.tta_outer_iters, K=args.K, V=V,
+                       S=S, seed=p.seed, t0=1, step=0.0, n_pow=30, reuse_b=False, x=x,
+                       x_ref=x_inf)
+    sk = summarize(rs, 1, args.K, 0, 31)
+    sk["pca_ms"] = pca_ms
+    if sk.get("converged"):
+        sk["total_ms"] += pca_ms
+    log(f"sketched (Alg. 1, K={args.K}): {sk}")
+    res = {"threshold": thr, "x_inf": ref, "full_coil": full, "sketched": sk,
+           "sketched_learned": None}
+    if full.get("converged") and sk.get("converged"):
+        res["speedup_total"] = full["total_ms"] / sk["total_ms"]
+        res["speedup_loop"] = full["loop_ms"] / sk["loop_ms"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +167,12 @@ def main():
     ap.add_argument("--K", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--small", action="store_true", help="48^3 instance (quick check)")
+    ap.add_argument("--no-tta", action="store_true", help="skip the time-to-accuracy runs")
+    ap.add_argument("--tta-thr", type=float, default=1e-3)
+    ap.add_argument("--tta-ref-iters", type=int, default=600)
+    ap.add_argument("--tta-chunk", type=int, default=100)
+    ap.add_argument("--tta-full-iters", type=int, default=400)
+    ap.add_argument("--tta-outer-iters", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -220,6 +311,9 @@ def main():
         "kernels": kern,
         "roofline": roof,
     }
+    if not args.no_tta:
+        log("time-to-accuracy runs")
+        out["time_to_accuracy"] = time_to_accuracy(ctx, y, p, args, log)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(p, Ch, geom)

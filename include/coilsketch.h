@@ -151,6 +151,9 @@ typedef struct {
    * iterations: full-coil normal applies, sketched normal applies, wavelet
    * prox, and forming the sketched maps */
   double ms_full_normal, ms_sketch_normal, ms_prox, ms_sketch;
+  /* GPU time before the first iteration: b = A^H y (unless reused), the PCA
+   * basis and first sketch (SKETCH), and the power iteration (step <= 0) */
+  double prep_ms;
 } cs_recon_stats;
 
 /* Reconstruction (Algorithm 1 or plain FISTA) of x from data y on the

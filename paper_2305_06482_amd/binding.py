@@ -85,6 +85,7 @@ class ReconStats(ctypes.Structure):
         ("ms_sketch_normal", ctypes.c_double),
         ("ms_prox", ctypes.c_double),
         ("ms_sketch", ctypes.c_double),
+        ("prep_ms", ctypes.c_double),
     ]
 
 
@@ -157,6 +158,7 @@ class ReconResult:
     ms_sketch_normal: float = 0.0
     ms_prox: float = 0.0
     ms_sketch: float = 0.0
+    prep_ms: float = 0.0
     time_ms: list = field(default_factory=list)
     dist: list = field(default_factory=list)
 
@@ -331,7 +333,8 @@ class Context:
                            n_sketch_applies=st.n_sketch_applies, n_prox=st.n_prox,
                            total_ms=st.total_ms, ms_full_normal=st.ms_full_normal,
                            ms_sketch_normal=st.ms_sketch_normal, ms_prox=st.ms_prox,
-                           ms_sketch=st.ms_sketch, time_ms=list(tms[:T]),
+                           ms_sketch=st.ms_sketch, prep_ms=st.prep_ms,
+                           time_ms=list(tms[:T]),
                            dist=list(dist[:T]) if x_ref is not None else [])
 
     def prox_l1wav(self, v, tau, out=None):

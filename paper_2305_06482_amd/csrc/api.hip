@@ -731,6 +731,18 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
   float2* g = c->img[5];
   float2* v = c->img[6];
   float2* xn = c->img[7];
+  // pooled events taken by this call go back to the pool on every return path
+  struct PoolBack {
+    cs_ctx* c;
+    std::vector<hipEvent_t> evs;
+    ~PoolBack() {
+      for (auto q : evs) c->ev_pool.push_back(q);
+    }
+  } pooled{c, {}};
+  hipEvent_t ev_prep = pool_event(c);
+  if (!ev_prep) return fail(c, CS_EHIP, "event creation failed");
+  pooled.evs.push_back(ev_prep);
+  CS_HIP(c, hipEventRecord(ev_prep, c->stream));
   if (!p->reuse_b || !c->have_b) {
     CS_TRY(chunk_loop(c, C, op_adjoint, c->maps, y, b));
     c->have_b = true;
@@ -755,14 +767,24 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
   }
   const float a = (float)alpha;
   const float tau_l = (float)(alpha * p->lam);
-  std::vector<hipEvent_t> ev;
-  hipEvent_t ev0 = nullptr, ev_end = nullptr;
-  CS_HIP(c, hipEventCreate(&ev0));
-  CS_HIP(c, hipEventCreate(&ev_end));
-  ev.resize(std::max(1, p->T));
-  for (auto& q : ev) CS_HIP(c, hipEventCreate(&q));
-  std::vector<hipEvent_t> evd(ev.size());
-  for (auto& q : evd) CS_HIP(c, hipEventCreate(&q));
+  // per-call events, destroyed on every return path
+  struct Events {
+    std::vector<hipEvent_t> all;
+    ~Events() {
+      for (auto q : all) (void)hipEventDestroy(q);
+    }
+    hipEvent_t make() {
+      hipEvent_t q = nullptr;
+      if (hipEventCreate(&q) != hipSuccess) return nullptr;
+      all.push_back(q);
+      return q;
+    }
+  } owned;
+  hipEvent_t ev0 = owned.make(), ev_end = owned.make();
+  std::vector<hipEvent_t> ev(std::max(1, p->T)), evd(ev.size());
+  for (auto& q : ev) q = owned.make();
+  for (auto& q : evd) q = owned.make();
+  if (owned.all.size() != 2 + 2 * ev.size()) return fail(c, CS_EHIP, "event creation failed");
   const bool track = p->x_ref != nullptr;
   std::vector<double> dist_num(p->T, 0.0), dist_den(p->T, 1.0);
   // phase timing: events around each full / sketched normal apply, prox and
@@ -774,6 +796,8 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
   std::vector<Phase> phases;
   auto timed = [&](int kind, auto&& fn) -> int {
     Phase ph{kind, pool_event(c), pool_event(c)};
+    if (ph.a) pooled.evs.push_back(ph.a);
+    if (ph.b) pooled.evs.push_back(ph.b);
     if (!ph.a || !ph.b) return fail(c, CS_EHIP, "event creation failed");
     CS_HIP(c, hipEventRecord(ph.a, c->stream));
     const int r = fn();
@@ -853,18 +877,16 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
     if (st && st->dist && track)
       st->dist[it] = std::sqrt(dist_num[it]) / std::sqrt(dist_den[it]);
   }
-  float total = 0.f;
+  float total = 0.f, prep = 0.f;
   CS_HIP(c, hipEventElapsedTime(&total, ev0, ev_end));
-  for (auto& q : ev) (void)hipEventDestroy(q);
-  for (auto& q : evd) (void)hipEventDestroy(q);
-  (void)hipEventDestroy(ev0);
-  (void)hipEventDestroy(ev_end);
+  CS_HIP(c, hipEventElapsedTime(&prep, ev_prep, ev0));
   if (st) {
     st->alpha = alpha;
     st->n_full_applies = nfull;
     st->n_sketch_applies = nsk;
     st->n_prox = nprox;
     st->total_ms = total - excluded;
+    st->prep_ms = prep;
     double pms[4] = {0, 0, 0, 0};
     for (auto& ph : phases) {
       float ms = 0.f;
@@ -875,10 +897,6 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
     st->ms_sketch_normal = pms[1];
     st->ms_prox = pms[2];
     st->ms_sketch = pms[3];
-  }
-  for (auto& ph : phases) {
-    c->ev_pool.push_back(ph.a);
-    c->ev_pool.push_back(ph.b);
   }
   double chk[2];
   CS_TRY(vec_dot(c, x, x, D, chk));
