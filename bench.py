@@ -266,7 +266,12 @@ def main():
     kb_sk = kernel_bytes(geom, Ch)
     kb_full = kernel_bytes(geom, 16)
     kern = {}
+    # the gridding step is the spread kernel plus the merge of its partial
+    # tiles: its algorithmic bytes are charged to the pair
+    merge_ms = prof.get("spread_merge", (0.0, 0))[0]
     for name, (ms, cnt) in prof.items():
+        if name == "spread":
+            ms = ms + merge_ms
         entry = {"ms": ms, "launches": cnt}
         if name in kb_sk and cnt:
             per_sk = 6 if name == "fft_pass" else 1

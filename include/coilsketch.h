@@ -196,10 +196,11 @@ int cs_grid_shape(const cs_ctx* ctx, int m[3]);
  * every kernel launch while enabled.  Kernel kinds (index into the arrays):
  * 0 FFT axis pass, 1 interpolation, 2 spreading, 3 sample gather,
  * 4 wavelet axis pass, 5 soft threshold, 6 element-wise vector op,
- * 7 FP64 reduction, 8 covariance, 9 eigensolver, 10 coil mixing.
+ * 7 FP64 reduction, 8 covariance, 9 eigensolver, 10 coil mixing,
+ * 11 spreading merge (sum of the halo'd partial tiles).
  * cs_profile_read synchronises, writes the summed milliseconds and launch
  * counts per kind (host arrays of length CS_NKERNELS) and resets them. */
-#define CS_NKERNELS 11
+#define CS_NKERNELS 12
 int cs_profile_enable(cs_ctx* ctx, int on);
 int cs_profile_read(cs_ctx* ctx, double* ms, long long* count);
 

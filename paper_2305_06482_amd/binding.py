@@ -32,9 +32,9 @@ EXPORTED = [
     "cs_dwt", "cs_idwt", "cs_coil_mix", "cs_dot", "cs_power_iteration", "cs_grid_shape",
     "cs_profile_enable", "cs_profile_read",
 ]
-NKERNELS = 11
+NKERNELS = 12
 KERNEL_KINDS = ["fft_pass", "interp", "spread", "gather", "wavelet", "soft", "vec", "reduce",
-                "covariance", "eigensolver", "coil_mix"]
+                "covariance", "eigensolver", "coil_mix", "spread_merge"]
 
 
 class CSError(RuntimeError):

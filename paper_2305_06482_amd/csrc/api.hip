@@ -553,8 +553,8 @@ void cs_destroy(cs_ctx* c) {
   fr(c->gridA); fr(c->gridB); fr(c->vbuf); fr(c->red); fr(c->red_out);
   fr(c->cov_part); fr(c->cov); fr(c->eig_dev); fr(c->vmaps); fr(c->smaps);
   fr(c->wav1); fr(c->wav2); fr(c->mask); fr(c->rec); fr(c->dcf_orig);
-  fr(c->tile_off); fr(c->tile_list); fr(c->mixB); fr(c->ones);
-  fr(c->items); fr(c->merges); fr(c->partial);
+  fr(c->mixB); fr(c->ones);
+  fr(c->items); fr(c->item_off); fr(c->partial);
   for (int a = 0; a < 3; ++a) fr(c->da[a]);
   fr(c->dp_z); fr(c->dp_y); fr(c->da_y1d);
   for (auto* p : c->img) fr(p);
@@ -599,12 +599,11 @@ int cs_set_operator(cs_ctx* c, const void* maps, const uint8_t* mask, const floa
     if (!coords) return fail(c, CS_EINVAL, "non-Cartesian operator needs coordinates");
     if (c->rec) {
       CS_HIP(c, hipFree(c->rec)); c->rec = nullptr;
-      CS_HIP(c, hipFree(c->tile_off)); c->tile_off = nullptr;
-      CS_HIP(c, hipFree(c->tile_list)); c->tile_list = nullptr;
       CS_HIP(c, hipFree(c->items)); c->items = nullptr;
-      CS_HIP(c, hipFree(c->merges)); c->merges = nullptr;
+      CS_HIP(c, hipFree(c->item_off)); c->item_off = nullptr;
       CS_HIP(c, hipFree(c->partial)); c->partial = nullptr;
-      c->n_items = c->n_merges = 0;
+      c->n_items = 0;
+      c->partial_elems = 0;
     }
     if (c->dcf_orig) {
       CS_HIP(c, hipFree(c->dcf_orig));

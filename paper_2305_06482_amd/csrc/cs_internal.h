@@ -104,17 +104,15 @@ struct cs_ctx {
   // non-Cartesian
   cs::SampleRec* rec = nullptr;   // [N] sorted
   float* dcf_orig = nullptr;      // [N] caller order (nullptr: w = 1)
-  int tile[3] = {1, 1, 1};        // tile size (tz, ty, tx)
+  int tile[3] = {1, 1, 1};        // spread tile size (tz, ty, tx)
   int ntile[3] = {1, 1, 1};
   long long ntiles = 0;
-  int* tile_off = nullptr;        // [ntiles + 1]
-  int* tile_list = nullptr;
-  int4* items = nullptr;          // spread work items (tile, kbeg, kend, slot)
+  int4* items = nullptr;          // spread work items (tile, kbeg, kend, slot), heavy first
   long long n_items = 0;
-  int4* merges = nullptr;         // split tiles (tile, first slot, slots, 0)
-  long long n_merges = 0;
-  float2* partial = nullptr;      // partial tiles of split tiles
-  int spread_nw = 4;              // waves per spread work-group
+  int* item_off = nullptr;        // [ntiles + 1]: slots of tile t are item_off[t]..[t+1]
+  float2* partial = nullptr;      // halo'd partial tile of every slot
+  size_t partial_elems = 0;       // float2 capacity of `partial`
+  int spread_cfg = 0;             // spread work-group shape (see launch_spread)
 
   // work buffers
   float2* gridA = nullptr;        // M * kCoilChunk
@@ -176,7 +174,7 @@ int fail(cs_ctx* c, int code, const std::string& msg);
 // kernel kinds for event timing (see cs_profile_read)
 enum {
   K_PASS = 0, K_INTERP, K_SPREAD, K_GATHER, K_WAVELET, K_SOFT, K_VEC, K_REDUCE,
-  K_COV, K_EIG, K_MIX
+  K_COV, K_EIG, K_MIX, K_MERGE
 };
 void prof_begin(cs_ctx* c, int kind);
 void prof_end(cs_ctx* c);

@@ -5,19 +5,22 @@
 // Set-up (once per operator, host): each sample's grid coordinate
 // u_a = k_a m_a / n_a gives its first tap floor(u_a) - 1 and the four
 // per-axis kernel weights phi(u_a - g) (FP64, stored as FP32).  Samples are
-// sorted by the 8x8x8 (3D) or 16x16 (2D) grid tile that holds their first tap,
-// and every tile gets the list of samples whose 4^d footprint reaches it.
+// sorted by the 8x8x8 (3D) or 16x16 (2D) grid tile that holds their first
+// tap, then by that tap, and each tile's samples are cut into work items of
+// at most 2048 samples.
 //
 // interp: one thread per sorted sample gathers the 4^d taps of every coil of
 //         a coil chunk (coil-fastest grid, so each tap is one contiguous
 //         vector of coils).
-// spread: one work-group per output tile accumulates, in LDS, the
-//         contributions of the samples on its list that land inside the tile,
-//         one sample at a time with one lane per tap.  Within a LDS
-//         instruction all lanes address distinct voxels and a wave executes
-//         its LDS instructions in order, so the summation order of every voxel
-//         is fixed: the result is deterministic and no global atomics are
-//         used.  Every voxel of the tile is then written once.
+// spread: one work-group per work item and coil group accumulates, in LDS,
+//         its samples into the tile grown by the 3-voxel reach of the kernel
+//         (each sample is handled once), one sample at a time with one lane
+//         per tap.  Within a LDS instruction all lanes address distinct
+//         voxels and a wave executes its LDS instructions in order, so every
+//         voxel's summation order is fixed.  The grown tile is written to the
+//         item's slot, and a merge kernel sums, for every grid voxel, the
+//         slots that cover it in a fixed order: deterministic, and no global
+//         atomics.
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -135,83 +138,89 @@ __device__ __forceinline__ float sel4(const float* w, int i) {
   return i == 0 ? w[0] : (i == 1 ? w[1] : (i == 2 ? w[2] : w[3]));
 }
 
-// Tile geometry of the spread: 8x8xTZ3 (3D, TZ3 = 4 or 8) or 16x16 (2D)
-// voxels.  The LDS accumulator is planar per (coil, re/im) with voxel offset
-// lz * PZ + ly * PY + lx; PY = 8, PZ = 68 (3D) and PY = 20 (2D) make the 32
-// lanes of each half-wave (one lane per tap) hit 32 distinct banks.
-template <int NDIM, int TZ3>
-struct SpreadTile {
+// Halo'd spread tile: every sample belongs to the one tile that holds its
+// first tap, and its 4^d footprint stays inside the tile grown by 3 voxels
+// along each axis.  The LDS accumulator is planar per (coil, re/im) with
+// voxel offset lz * PZ + ly * PY + lx: dense in 3D (the 64 taps of a sample
+// meet at most two per bank, and only when a run is flushed) and with row
+// pitch 20 in 2D (16 taps in distinct banks).
+template <int NDIM>
+struct Halo {
   static constexpr int TX = NDIM == 3 ? 8 : 16;
   static constexpr int TY = NDIM == 3 ? 8 : 16;
-  static constexpr int TZ = NDIM == 3 ? TZ3 : 1;
-  static constexpr int PY = NDIM == 3 ? 8 : 20;
-  static constexpr int PZ = NDIM == 3 ? 68 : 0;
-  static constexpr int PLANE = NDIM == 3 ? TZ * PZ : TY * PY;
-  static constexpr int NVOX = TX * TY * TZ;
+  static constexpr int TZ = NDIM == 3 ? 8 : 1;
+  static constexpr int EX = TX + 3, EY = TY + 3, EZ = NDIM == 3 ? TZ + 3 : 1;
+  static constexpr int EXT = EX * EY * EZ;  // voxels of a partial tile
+  static constexpr int PY = NDIM == 3 ? EX : 20;
+  static constexpr int PZ = NDIM == 3 ? EX * EY : 0;
+  static constexpr int PLANE = (EZ - 1) * PZ + (EY - 1) * PY + EX + 1;
+  static constexpr int NTAPS = NDIM == 3 ? 64 : 16;
+  static constexpr int LPC = 64 / NTAPS;  // coil slots per wave
 };
 
-constexpr int kSpreadBatch = 64;   // samples staged in LDS per step
+constexpr int kSpreadBatch = 64;  // samples staged in LDS per step
+constexpr int kSpreadRecPitch = 13;  // staged record: packed first tap + 12 weights
 
-// One work item = one output tile and a contiguous chunk of its sample list
-// (samples whose footprint reaches the tile, in sorted order).  Lane l of
-// each wave owns tap (l & 3, (l >> 2) & 3, l >> 4) of the current sample.
-// Consecutive samples with the same first tap touch the same voxels, so a
-// lane accumulates such a run in registers and adds the run's sum into the
-// LDS tile once (one ds_add per coil and part; the lanes of one instruction
-// address distinct voxels, and a wave issues its LDS operations in order, so
-// every voxel's summation order is fixed).  Items that cover a whole tile
-// write it to the grid; items of a split tile write a partial tile that the
-// merge kernel sums in item order.
-template <int NDIM, int TZ3, int NW, int CBW>
+// One work-group = one work item (a contiguous range of the samples of one
+// tile, in sorted order) and one group of CG = NW * LPC * CW coils.  Lane l
+// of a wave owns tap l % NTAPS of the current sample for CW coils of the
+// group.  Consecutive samples with the same first tap touch the same voxels:
+// a lane sums such a run in registers and adds the sum into the LDS tile
+// once.  The lanes of one LDS instruction address distinct voxels, waves own
+// distinct coils, and a wave issues its LDS operations in order, so the
+// summation order of every voxel is fixed.  The halo'd tile is written to
+// the item's slot; k_spread_merge sums the slots that cover each voxel.
+template <int NDIM, int NW, int CW>
 __global__ __launch_bounds__(64 * NW) void k_spread(
     const float2* __restrict__ V, int cb, const SampleRec* __restrict__ rec,
-    const int4* __restrict__ items, const int* __restrict__ tile_list, int ntx, int nty,
-    int mx, int my, int mz, float2* __restrict__ G, float2* __restrict__ partial) {
-  using T = SpreadTile<NDIM, TZ3>;
-  constexpr int NT = 64 * NW;  // NW waves, each owning a contiguous share of the coils
+    const int4* __restrict__ items, int ntx, int nty, float2* __restrict__ P) {
+  using H = Halo<NDIM>;
+  constexpr int NT = 64 * NW;
+  constexpr int CG = NW * H::LPC * CW;
+  constexpr int SB = kSpreadBatch, SRP = kSpreadRecPitch;
+  constexpr int VPT = CG * SB / NT;  // staged values per thread
   extern __shared__ float lds[];
-  constexpr int SRP = 17;  // staged record pitch (odd: conflict-free writes)
-  float* acc = lds;                                   // [cb][2][PLANE]
-  float* srec = lds + (size_t)cb * 2 * T::PLANE;      // [batch][SRP]
-  float2* sv = reinterpret_cast<float2*>(srec + kSpreadBatch * SRP + 1);  // [batch][NW CBW]
+  float* acc = lds;                                         // [CG][2][PLANE]
+  float* srec = acc + (size_t)CG * 2 * H::PLANE;            // [SB][SRP]
+  // staged values: separate re / im planes [SB][2 CG] with the coils two
+  // dwords apart, so that every broadcast read below is a single dword
+  // (wider same-address LDS reads are much slower on this hardware)
+  float* sre = srec + SB * SRP;
+  float* sim = sre + SB * 2 * CG;
+  __shared__ int s_rs[SB];  // run starts of the staged batch
+  __shared__ int s_nr;
 
   const int4 it = items[blockIdx.x];
   const int tile = it.x, kbeg = it.y, kend = it.z, slot = it.w;
+  const int g = blockIdx.y, ng = gridDim.y;
+  const int cg0 = g * CG, cga = min(CG, cb - cg0);
   const int ix = tile % ntx, iy = (tile / ntx) % nty, iz = tile / (ntx * nty);
-  const int x0 = ix * T::TX, y0 = iy * T::TY, z0 = iz * T::TZ;
-  const int ex = min(T::TX, mx - x0), ey = min(T::TY, my - y0), ez = min(T::TZ, mz - z0);
-  const int tid = threadIdx.x;
-  for (int i = tid; i < cb * 2 * T::PLANE; i += NT) acc[i] = 0.f;
+  const int x0 = ix * H::TX, y0 = iy * H::TY, z0 = iz * H::TZ;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int i = tid; i < CG * 2 * H::PLANE; i += NT) acc[i] = 0.f;
 
-  const int wave = tid >> 6, lane = tid & 63;
-  const int cbw = (cb + NW - 1) / NW;
-  const int c_lo = wave * cbw;
-  const int c_n = max(0, min(cb, c_lo + cbw) - c_lo);
-  const int dx = lane & 3, dy = (lane >> 2) & 3, dz = lane >> 4;
-  const bool lane_ok = NDIM == 3 || dz == 0;
-
-  float2 racc[CBW];
+  const int tap = lane % H::NTAPS, cslot = lane / H::NTAPS;
+  const int dx = tap & 3, dy = (tap >> 2) & 3, dz = tap >> 4;
+  const int q0 = (wave * H::LPC + cslot) * CW;  // first group coil of this lane
+  float2 racc[CW];
 #pragma unroll
-  for (int q = 0; q < CBW; ++q) racc[q] = make_float2(0.f, 0.f);
-  int rbx = -1, rby = -1, rbz = -1;
-  int raddr = 0;
-  bool rin = false;
+  for (int q = 0; q < CW; ++q) racc[q] = make_float2(0.f, 0.f);
+  int rkey = -1, raddr = 0;
 
-  __shared__ int s_rs[kSpreadBatch];  // run starts of the staged batch
-  __shared__ int s_nr;
-  constexpr int pitch = NW * CBW;     // staged value row; each wave reads CBW slots
-
-  // Staging is double-buffered through registers: the loads of batch b + 1
-  // are issued before batch b is processed.  Thread t < 64 fetches sample t's
-  // record; thread t fetches coil share (t % NW) of sample t / NW.
+  // staging, double-buffered through registers: thread t < SB fetches the
+  // record of sample t of the batch; value e = t + j NT is (sample e / CG,
+  // group coil e % CG)
+  // (the loaded values are only consumed after the next barrier, so the
+  // loads stay in flight while the current batch is processed)
   int pb[3] = {0, 0, 0};
   float pw[12];
-  float2 pv[CBW];
-  const int vs = tid / NW, vh = tid % NW;
+  float2 pv[VPT];
   auto prefetch = [&](int k0, int n) {
     if (tid < n) {
-      const SampleRec& r = rec[tile_list[k0 + tid]];
-      pb[0] = r.bx; pb[1] = r.by; pb[2] = r.bz;
+      const SampleRec& r = rec[k0 + tid];
+      pb[0] = r.bx;
+      pb[1] = r.by;
+      pb[2] = r.bz;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         pw[q] = r.wx[q];
@@ -219,157 +228,174 @@ __global__ __launch_bounds__(64 * NW) void k_spread(
         pw[8 + q] = r.wz[q];
       }
     }
-    if (vs < n) {
-      const float2* src = V + (long long)tile_list[k0 + vs] * cb + vh * cbw;
-      const int lim = cb - vh * cbw;
 #pragma unroll
-      for (int q = 0; q < CBW; ++q)
-        if (q < lim && q < cbw) pv[q] = src[q];
+    for (int j = 0; j < VPT; ++j) {
+      const int e = tid + j * NT, s = e / CG, q = e - s * CG;
+      pv[j] = (s < n && q < cga) ? V[(long long)(k0 + s) * cb + cg0 + q]
+                                 : make_float2(0.f, 0.f);
     }
   };
-  if (kbeg < kend) prefetch(kbeg, min(kSpreadBatch, kend - kbeg));
+  if (kbeg < kend) prefetch(kbeg, min(SB, kend - kbeg));
 
-  for (int k0 = kbeg; k0 < kend; k0 += kSpreadBatch) {
-    const int n = min(kSpreadBatch, kend - k0);
+  for (int k0 = kbeg; k0 < kend; k0 += SB) {
+    const int n = min(SB, kend - k0);
     __syncthreads();  // previous batch consumed (and accumulator zeroed)
+    const int pkey = (pb[0] - x0) | ((pb[1] - y0) << 8) | ((pb[2] - z0) << 16);
     if (tid < n) {
       float* d = srec + tid * SRP;
-      d[0] = __int_as_float(pb[0]);
-      d[1] = __int_as_float(pb[1]);
-      d[2] = __int_as_float(pb[2]);
+      d[0] = __int_as_float(pkey);
 #pragma unroll
-      for (int q = 0; q < 12; ++q) d[4 + q] = pw[q];
+      for (int q = 0; q < 12; ++q) d[1 + q] = pw[q];
     }
-    if (vs < n) {
-      // each thread writes only its own cbw columns (the halves must not overlap)
-      float2* dst = sv + vs * pitch + vh * cbw;
 #pragma unroll
-      for (int q = 0; q < CBW; ++q)
-        if (q < cbw) dst[q] = pv[q];
+    for (int j = 0; j < VPT; ++j) {
+      sre[2 * (tid + j * NT)] = pv[j].x;
+      sim[2 * (tid + j * NT)] = pv[j].y;
     }
     // run starts: sample s opens a run when its first tap differs from the
     // previous sample's (or from the run carried over from the last batch)
     if (tid < 64) {
-      const int qx = __shfl_up(pb[0], 1), qy = __shfl_up(pb[1], 1), qz = __shfl_up(pb[2], 1);
-      const int pbx = tid > 0 ? qx : rbx, pby = tid > 0 ? qy : rby, pbz = tid > 0 ? qz : rbz;
-      const bool start = tid < n && (pb[0] != pbx || pb[1] != pby || pb[2] != pbz);
+      const int prev = __shfl_up(pkey, 1);
+      const bool start = tid < n && pkey != (tid > 0 ? prev : rkey);
       const unsigned long long mask = __ballot(start);
       if (start) s_rs[__popcll(mask & ((1ull << tid) - 1ull))] = tid;
       if (tid == 0) s_nr = __popcll(mask);
     }
     __syncthreads();
-    if (k0 + kSpreadBatch < kend)
-      prefetch(k0 + kSpreadBatch, min(kSpreadBatch, kend - k0 - kSpreadBatch));
+    if (k0 + SB < kend) prefetch(k0 + SB, min(SB, kend - k0 - SB));
     const int nr = s_nr;
     int s = 0;
     for (int r = -1; r < nr; ++r) {
       const int s1 = (r + 1 < nr) ? s_rs[r + 1] : n;
       if (r >= 0) {
         // close the current run, open the one starting at s
-        if (rin) {
+        if (rkey >= 0) {
 #pragma unroll
-          for (int q = 0; q < CBW; ++q) {
-            if (q < c_n) {
-              float* pl = acc + (size_t)(c_lo + q) * 2 * T::PLANE + raddr;
-              atomicAdd(pl, racc[q].x);
-              atomicAdd(pl + T::PLANE, racc[q].y);
-            }
+          for (int q = 0; q < CW; ++q) {
+            // plain read-add-write: this lane is the only one touching
+            // this voxel of this coil until the next flush
+            float* pl = acc + (size_t)(q0 + q) * 2 * H::PLANE + raddr;
+            pl[0] += racc[q].x;
+            pl[H::PLANE] += racc[q].y;
+            racc[q] = make_float2(0.f, 0.f);
           }
         }
-#pragma unroll
-        for (int q = 0; q < CBW; ++q) racc[q] = make_float2(0.f, 0.f);
-        const float* d = srec + s * SRP;
-        rbx = __float_as_int(d[0]); rby = __float_as_int(d[1]); rbz = __float_as_int(d[2]);
-        int gx = rbx + dx;
-        if (gx >= mx) gx -= mx;
-        int gy = rby + dy;
-        if (gy >= my) gy -= my;
-        int gz = NDIM == 3 ? rbz + dz : 0;
-        if (gz >= mz) gz -= mz;
-        const int lx = gx - x0, ly = gy - y0, lz = gz - z0;
-        rin = lane_ok && (unsigned)lx < (unsigned)ex && (unsigned)ly < (unsigned)ey &&
-              (unsigned)lz < (unsigned)ez;
-        raddr = lz * T::PZ + ly * T::PY + lx;
+        rkey = __float_as_int(srec[s * SRP]);
+        const int lx = (rkey & 0xff) + dx, ly = ((rkey >> 8) & 0xff) + dy,
+                  lz = NDIM == 3 ? (rkey >> 16) + dz : 0;
+        raddr = lz * H::PZ + ly * H::PY + lx;
       }
       // samples of the run: register accumulation, no branches
 #pragma unroll 2
       for (; s < s1; ++s) {
         const float* d = srec + s * SRP;
-        float w = d[4 + dx] * d[8 + dy];
-        if (NDIM == 3) w *= d[12 + dz];
-        const float2* v = sv + s * pitch + c_lo;
+        float w = d[1 + dx] * d[5 + dy];
+        if (NDIM == 3) w *= d[9 + dz];
+        const int vb = 2 * (s * CG + q0);
 #pragma unroll
-        for (int q = 0; q < CBW; ++q) {
-          const float2 val = v[q];
-          racc[q].x += w * val.x;
-          racc[q].y += w * val.y;
+        for (int q = 0; q < CW; ++q) {
+          racc[q].x += w * sre[vb + 2 * q];
+          racc[q].y += w * sim[vb + 2 * q];
         }
       }
     }
   }
-  if (rin) {
+  if (rkey >= 0) {
 #pragma unroll
-    for (int q = 0; q < CBW; ++q) {
-      if (q < c_n) {
-        float* pl = acc + (size_t)(c_lo + q) * 2 * T::PLANE + raddr;
-        atomicAdd(pl, racc[q].x);
-        atomicAdd(pl + T::PLANE, racc[q].y);
-      }
+    for (int q = 0; q < CW; ++q) {
+      float* pl = acc + (size_t)(q0 + q) * 2 * H::PLANE + raddr;
+      pl[0] += racc[q].x;
+      pl[H::PLANE] += racc[q].y;
     }
   }
   __syncthreads();
-  // write-out: element i = voxel v (tile order) * cb + coil; the quotient
-  // i / cb (i < 2^13, cb <= 16) is exact in float with the half offset
-  const float inv_cb = 1.0f / (float)cb;
-  for (int i = tid; i < T::NVOX * cb; i += NT) {
-    const int v = (int)(((float)i + 0.5f) * inv_cb);
-    const int c = i - v * cb;
-    const int lx = v % T::TX, ly = (v / T::TX) % T::TY, lz = v / (T::TX * T::TY);
-    if (lx >= ex || ly >= ey || lz >= ez) continue;
-    const int e = lz * T::PZ + ly * T::PY + lx;
-    const float2 val = make_float2(acc[(size_t)c * 2 * T::PLANE + e],
-                                   acc[(size_t)c * 2 * T::PLANE + T::PLANE + e]);
-    if (slot < 0) {
-      G[(((long long)(z0 + lz) * my + (y0 + ly)) * mx + (x0 + lx)) * cb + c] = val;
-    } else {
-      const int tv = (lz * T::TY + ly) * T::TX + lx;
-      partial[((long long)slot * T::NVOX + tv) * cb + c] = val;
-    }
+  // write-out: slot layout [slot][group][EXT][CG]
+  float2* dst = P + ((size_t)slot * ng + g) * H::EXT * CG;
+  for (int i = tid; i < H::EXT * CG; i += NT) {
+    const int e = i / CG, q = i - e * CG;
+    const int lx = e % H::EX, ly = (e / H::EX) % H::EY, lz = e / (H::EX * H::EY);
+    const int a = lz * H::PZ + ly * H::PY + lx;
+    dst[i] = make_float2(acc[(size_t)q * 2 * H::PLANE + a],
+                         acc[(size_t)q * 2 * H::PLANE + H::PLANE + a]);
   }
 }
 
-// Sum the partial tiles of split tiles in item order.  merges[i] =
-// (tile, first slot, slot count, 0).
-template <int NDIM, int TZ3>
-__global__ void k_spread_merge(const int4* __restrict__ merges, const float2* __restrict__ partial,
-                               int cb, int ntx, int nty, int mx, int my, int mz,
-                               float2* __restrict__ G) {
-  using T = SpreadTile<NDIM, TZ3>;
-  // block b handles elements [part * 256, part * 256 + 256) of merge b / nparts
-  const int nparts = (T::NVOX * cb + 255) / 256;
-  const int4 m = merges[blockIdx.x / nparts];
-  const int part = blockIdx.x % nparts;
-  const int tile = m.x;
-  const int ix = tile % ntx, iy = (tile / ntx) % nty, iz = tile / (ntx * nty);
-  const int x0 = ix * T::TX, y0 = iy * T::TY, z0 = iz * T::TZ;
-  const int ex = min(T::TX, mx - x0), ey = min(T::TY, my - y0), ez = min(T::TZ, mz - z0);
-  const int i = part * 256 + threadIdx.x;
-  if (i >= T::NVOX * cb) return;
-  const int v = (int)(((float)i + 0.5f) / (float)cb);  // exact for i < 2^13
-  const int c = i - v * cb;
-  const int lx = v % T::TX, ly = (v / T::TX) % T::TY, lz = v / (T::TX * T::TY);
-  if (lx >= ex || ly >= ey || lz >= ez) return;
-  const int tv = v;
-  const float2* p = partial + ((long long)m.y * T::NVOX + tv) * cb + c;
-  const long long step = (long long)T::NVOX * cb;
-  float2 s = make_float2(0.f, 0.f);
-#pragma unroll 8
-  for (int q = 0; q < m.z; ++q) {
-    const float2 pv = p[q * step];
-    s.x += pv.x;
-    s.y += pv.y;
+// Halo'd tiles that reach grid coordinate g along one axis (tile size T,
+// grid length m, nt tiles, g in tile ig): pairs (tile, local coordinate in
+// the halo'd tile), in a fixed order.  Returns the count (at most 6).
+__device__ __forceinline__ int halo_cover(int g, int ig, int nt, int T, int m, int* ct,
+                                          int* cd) {
+  int n = 0;
+  const int kmax = min(2, nt - 1);
+  for (int k = 0; k <= kmax; ++k) {
+    int t = ig - k;
+    if (t < 0) t += nt;
+    const int x0 = t * T, ex = min(T, m - x0);
+    int d = g - x0;
+    if (d < 0) d += m;
+    for (; d < ex + 3 && n < 6; d += m) {
+      ct[n] = t;
+      cd[n] = d;
+      ++n;
+    }
   }
-  G[(((long long)(z0 + lz) * my + (y0 + ly)) * mx + (x0 + lx)) * cb + c] = s;
+  return n;
+}
+
+// G = sum of the partial tiles that cover each voxel, in a fixed order
+// (covering tile z, y, x, then slot).  One thread per voxel sums all coils;
+// every voxel of the grid is written.
+template <int NDIM, int CG>
+__global__ __launch_bounds__(256) void k_spread_merge(
+    const float2* __restrict__ P, const int* __restrict__ item_off, int cb, int ng, int ntx,
+    int nty, int ntz, int mx, int my, int mz, float2* __restrict__ G) {
+  using H = Halo<NDIM>;
+  constexpr int TV = H::TX * H::TY * H::TZ;
+  constexpr int BPT = (TV + 255) / 256;  // blocks per tile
+  constexpr int NGMAX = (kCoilChunk + CG - 1) / CG;
+  const int tile = blockIdx.x / BPT;
+  const int v = (blockIdx.x - tile * BPT) * 256 + threadIdx.x;
+  if (v >= TV) return;
+  const int ix = tile % ntx, iy = (tile / ntx) % nty, iz = tile / (ntx * nty);
+  const int gx = ix * H::TX + v % H::TX, gy = iy * H::TY + (v / H::TX) % H::TY,
+            gz = iz * H::TZ + v / (H::TX * H::TY);
+  if (gx >= mx || gy >= my || gz >= mz) return;
+  int tx[6], dxs[6], ty[6], dys[6], tz[6], dzs[6];
+  const int nx_ = halo_cover(gx, ix, ntx, H::TX, mx, tx, dxs);
+  const int ny_ = halo_cover(gy, iy, nty, H::TY, my, ty, dys);
+  int nz_ = 1;
+  tz[0] = 0;
+  dzs[0] = 0;
+  if (NDIM == 3) nz_ = halo_cover(gz, iz, ntz, H::TZ, mz, tz, dzs);
+  float2 acc[NGMAX * CG];
+#pragma unroll
+  for (int c = 0; c < NGMAX * CG; ++c) acc[c] = make_float2(0.f, 0.f);
+  const size_t gstride = (size_t)H::EXT * CG;
+  for (int a = 0; a < nz_; ++a)
+    for (int b = 0; b < ny_; ++b)
+      for (int d = 0; d < nx_; ++d) {
+        const int t = (tz[a] * nty + ty[b]) * ntx + tx[d];
+        const int e = (dzs[a] * H::EY + dys[b]) * H::EX + dxs[d];
+        const int s1 = item_off[t + 1];
+        for (int sl = item_off[t]; sl < s1; ++sl) {
+          const float2* p = P + (size_t)sl * ng * gstride + (size_t)e * CG;
+#pragma unroll
+          for (int g = 0; g < NGMAX; ++g) {
+            if (g < ng) {
+#pragma unroll
+              for (int q = 0; q < CG; ++q) {
+                const float2 pv = p[g * gstride + q];
+                acc[g * CG + q].x += pv.x;
+                acc[g * CG + q].y += pv.y;
+              }
+            }
+          }
+        }
+      }
+  float2* out = G + (((long long)gz * my + gy) * mx + gx) * cb;
+#pragma unroll
+  for (int c = 0; c < NGMAX * CG; ++c)
+    if (c < cb) out[c] = acc[c];
 }
 
 __global__ void k_gather_samples(const float2* __restrict__ y, int ldc, int c0, int cb,
@@ -427,55 +453,74 @@ int launch_interp(cs_ctx* c, const float2* grid, int cb, int wmode, float2* out,
 }
 
 namespace {
-template <int NDIM, int TZ3, int NW, int CBW>
+template <int NDIM, int NW, int CW>
+constexpr int spread_cg() {
+  return NW * Halo<NDIM>::LPC * CW;
+}
+
+template <int NDIM, int NW, int CW>
+size_t spread_lds_bytes() {
+  using H = Halo<NDIM>;
+  constexpr int CG = spread_cg<NDIM, NW, CW>();
+  constexpr int SR = kSpreadBatch * kSpreadRecPitch;
+  return sizeof(float) * ((size_t)CG * 2 * H::PLANE + SR + (size_t)4 * kSpreadBatch * CG);
+}
+
+template <int NDIM, int NW, int CW>
 int spread_launch(cs_ctx* c, const float2* vals, int cb, float2* grid) {
-  using T = SpreadTile<NDIM, TZ3>;
-  const size_t lds = sizeof(float) * ((size_t)cb * 2 * T::PLANE + kSpreadBatch * 17 + 1) +
-                     sizeof(float2) * (size_t)kSpreadBatch * NW * CBW;
-  if (lds > 160 * 1024) return fail(c, CS_EINVAL, "spread tile does not fit in LDS");
-  auto kern = k_spread<NDIM, TZ3, NW, CBW>;
-  if (lds > 64 * 1024)
-    CS_HIP(c, hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds));
-  if (c->n_items > 0)
-    CS_KLAUNCH(c, K_SPREAD, kern, dim3((unsigned)c->n_items), dim3(64 * NW), lds, c->stream,
-               vals, cb, c->rec, c->items, c->tile_list, c->ntile[2], c->ntile[1], c->mx,
-               c->my, c->mz, grid, c->partial);
-  CS_HIP(c, hipGetLastError());
-  if (c->n_merges > 0) {
-    const long long nparts = (T::NVOX * cb + 255) / 256;
-    CS_KLAUNCH(c, K_SPREAD, (k_spread_merge<NDIM, TZ3>),
-               dim3((unsigned)(c->n_merges * nparts)), dim3(256), 0, c->stream, c->merges,
-               c->partial, cb, c->ntile[2], c->ntile[1], c->mx, c->my, c->mz, grid);
+  using H = Halo<NDIM>;
+  constexpr int CG = spread_cg<NDIM, NW, CW>();
+  const int ng = (cb + CG - 1) / CG;
+  if ((size_t)c->n_items * ng * H::EXT * CG > c->partial_elems)
+    return fail(c, CS_EINVAL, "spread partial buffer too small");
+  const size_t lds = spread_lds_bytes<NDIM, NW, CW>();
+  if (c->n_items > 0) {
+    auto kern = k_spread<NDIM, NW, CW>;
+    if (lds > 64 * 1024)
+      CS_HIP(c, hipFuncSetAttribute((const void*)kern,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    CS_KLAUNCH(c, K_SPREAD, kern, dim3((unsigned)c->n_items, (unsigned)ng), dim3(64 * NW), lds,
+               c->stream, vals, cb, c->rec, c->items, c->ntile[2], c->ntile[1], c->partial);
+    CS_HIP(c, hipGetLastError());
   }
+  constexpr long long TV = (long long)H::TX * H::TY * H::TZ;
+  const long long blocks = c->ntiles * ((TV + 255) / 256);
+  if (blocks > 0x7fffffffLL) return fail(c, CS_EINVAL, "spread merge grid too large");
+  CS_KLAUNCH(c, K_MERGE, (k_spread_merge<NDIM, CG>), dim3((unsigned)blocks), dim3(256), 0,
+             c->stream, c->partial, c->item_off, cb, ng, c->ntile[2], c->ntile[1],
+             c->ntile[0], c->mx, c->my, c->mz, grid);
   CS_HIP(c, hipGetLastError());
   return CS_OK;
 }
 
-template <int NDIM, int TZ3, int NW>
-int spread_cbw(cs_ctx* c, const float2* vals, int cb, float2* grid) {
-  const int cbw = (cb + NW - 1) / NW;  // coils per wave
-  if (cbw <= 2) return spread_launch<NDIM, TZ3, NW, 2>(c, vals, cb, grid);
-  if (cbw <= 4) return spread_launch<NDIM, TZ3, NW, 4>(c, vals, cb, grid);
-  if (cbw <= 6) return spread_launch<NDIM, TZ3, NW, 6>(c, vals, cb, grid);
-  if (cbw <= 8 || NW > 1) return spread_launch<NDIM, TZ3, NW, 8>(c, vals, cb, grid);
-  if (cbw <= 12) return spread_launch<NDIM, TZ3, 1, 12>(c, vals, cb, grid);
-  return spread_launch<NDIM, TZ3, 1, 16>(c, vals, cb, grid);
+// work-group shapes (waves NW, coils per lane CW); the coils of a group are
+// NW * CW (3D) or 4 NW CW (2D, four coil slots of 16 taps per wave)
+template <int NDIM>
+int spread_dispatch(cs_ctx* c, const float2* vals, int cb, float2* grid) {
+  switch (c->spread_cfg) {
+    case 1: return spread_launch<NDIM, 2, 2>(c, vals, cb, grid);
+    case 2: return spread_launch<NDIM, 2, 1>(c, vals, cb, grid);
+    case 3: return spread_launch<NDIM, 1, 4>(c, vals, cb, grid);
+    case 4: return spread_launch<NDIM, 4, 2>(c, vals, cb, grid);
+    case 5: return spread_launch<NDIM, 1, 3>(c, vals, cb, grid);
+    default: return spread_launch<NDIM, 4, 1>(c, vals, cb, grid);
+  }
 }
 
-template <int NDIM, int TZ3>
-int spread_nw(cs_ctx* c, const float2* vals, int cb, float2* grid) {
-  if (c->spread_nw == 1) return spread_cbw<NDIM, TZ3, 1>(c, vals, cb, grid);
-  return c->spread_nw == 2 ? spread_cbw<NDIM, TZ3, 2>(c, vals, cb, grid)
-                           : spread_cbw<NDIM, TZ3, 4>(c, vals, cb, grid);
+// largest coil-group size over the shapes above, for the partial buffer
+int spread_max_group_elems(int ndim) {
+  const int lpc = ndim == 3 ? 1 : 4;
+  const int cgs[6] = {4 * lpc, 4 * lpc, 2 * lpc, 4 * lpc, 8 * lpc, 3 * lpc};
+  int best = 0;
+  for (int cg : cgs) best = std::max(best, ((kCoilChunk + cg - 1) / cg) * cg);
+  return best;
 }
 }  // namespace
 
 int launch_spread(cs_ctx* c, const float2* vals, int cb, float2* grid) {
   if (cb < 1 || cb > kCoilChunk) return fail(c, CS_EINVAL, "spread coil chunk");
-  if (c->ndim == 2) return spread_nw<2, 1>(c, vals, cb, grid);
-  return c->tile[0] == 4 ? spread_nw<3, 4>(c, vals, cb, grid)
-                         : spread_nw<3, 8>(c, vals, cb, grid);
+  return c->ndim == 3 ? spread_dispatch<3>(c, vals, cb, grid)
+                      : spread_dispatch<2>(c, vals, cb, grid);
 }
 
 int launch_gather_samples(cs_ctx* c, const float2* y, int ldc, int c0, int cb,
@@ -492,6 +537,7 @@ int launch_gather_samples(cs_ctx* c, const float2* y, int ldc, int c0, int cb,
 int setup_noncart(cs_ctx* c, const float* coords_dev, const float* dcf_dev) {
   const long long N = c->N;
   const int nd = c->ndim;
+  if (N > 0x7fffffffLL) return fail(c, CS_EINVAL, "more than 2^31 - 1 samples");
   std::vector<float> coords((size_t)N * nd), dcf;
   CS_HIP(c, hipMemcpy(coords.data(), coords_dev, sizeof(float) * N * nd,
                       hipMemcpyDeviceToHost));
@@ -505,22 +551,15 @@ int setup_noncart(cs_ctx* c, const float* coords_dev, const float* dcf_dev) {
   const int m[3] = {c->mz, c->my, c->mx};
   const double W = 4.0, beta = c->beta;
 
-  // tiles
-  if (nd == 3) {
-    // tile depth 4 (default) or 8, and waves per spread work-group (2 by
-    // default, or 1 or 4) -- the defaults measured fastest on the 3D cones
-    // workload:
-    // tuning knobs, CS_SPREAD_TZ and CS_SPREAD_NW in the environment
-    const char* tz = std::getenv("CS_SPREAD_TZ");
-    c->tile[0] = (tz && std::atoi(tz) == 8) ? 8 : 4;
-    c->tile[1] = 8;
-    c->tile[2] = 8;
-    const char* nw = std::getenv("CS_SPREAD_NW");
-    const int nwv = nw ? std::atoi(nw) : 2;
-    c->spread_nw = (nwv == 1 || nwv == 4) ? nwv : 2;
-  } else {
-    c->tile[0] = 1; c->tile[1] = 16; c->tile[2] = 16;
-  }
+  // spread tiles: 8x8x8 (3D) or 16x16 (2D) voxels; the work-group shape is
+  // a tuning knob (CS_SPREAD_CFG in the environment, see spread_dispatch)
+  c->tile[0] = nd == 3 ? 8 : 1;
+  c->tile[1] = nd == 3 ? 8 : 16;
+  c->tile[2] = nd == 3 ? 8 : 16;
+  for (int a = 3 - nd; a < 3; ++a)
+    if (m[a] < 4) return fail(c, CS_EINVAL, "NUFFT grid shorter than the kernel");
+  const char* cfg = std::getenv("CS_SPREAD_CFG");
+  c->spread_cfg = cfg ? std::atoi(cfg) : 0;
   for (int a = 0; a < 3; ++a) c->ntile[a] = (m[a] + c->tile[a] - 1) / c->tile[a];
   c->ntiles = (long long)c->ntile[0] * c->ntile[1] * c->ntile[2];
 
@@ -564,95 +603,45 @@ int setup_noncart(cs_ctx* c, const float* coords_dev, const float* dcf_dev) {
   std::vector<SampleRec> srec(N);
   for (long long j = 0; j < N; ++j) srec[j] = rec[order[j]];
 
-  // tile lists: every tile reached by a sample's footprint
-  std::vector<int> cnt(c->ntiles + 1, 0);
-  auto tiles_of = [&](const SampleRec& r, long long* out) -> int {
-    int lists[3][2], nl[3];
-    const int b[3] = {r.bz, r.by, r.bx};
-    for (int a = 0; a < 3; ++a) {
-      const int span = (a == 0 && nd == 2) ? 1 : 4;
-      nl[a] = 0;
-      for (int d = 0; d < span; ++d) {
-        int g = b[a] + d;
-        if (g >= m[a]) g -= m[a];
-        const int ti = g / c->tile[a];
-        bool seen = false;
-        for (int q = 0; q < nl[a]; ++q) seen |= lists[a][q] == ti;
-        if (!seen) lists[a][nl[a]++] = ti;
-      }
-    }
-    int k = 0;
-    for (int i0 = 0; i0 < nl[0]; ++i0)
-      for (int i1 = 0; i1 < nl[1]; ++i1)
-        for (int i2 = 0; i2 < nl[2]; ++i2)
-          out[k++] = ((long long)lists[0][i0] * c->ntile[1] + lists[1][i1]) * c->ntile[2] +
-                     lists[2][i2];
-    return k;
-  };
-  long long tl[8];
-  long long nnz = 0;
-  for (long long j = 0; j < N; ++j) {
-    const int k = tiles_of(srec[j], tl);
-    for (int q = 0; q < k; ++q) cnt[tl[q] + 1]++;
-    nnz += k;
-  }
-  if (nnz > 0x7fffffffLL) return fail(c, CS_EINVAL, "too many samples for tile lists");
-  for (long long t = 0; t < c->ntiles; ++t) cnt[t + 1] += cnt[t];
-  std::vector<int> fillpos(cnt.begin(), cnt.end() - 1);
-  std::vector<int> list(nnz);
-  for (long long j = 0; j < N; ++j) {
-    const int k = tiles_of(srec[j], tl);
-    for (int q = 0; q < k; ++q) list[fillpos[tl[q]]++] = (int)j;
-  }
+  // samples per tile (each sample belongs to the tile of its first tap)
+  std::vector<long long> toff(c->ntiles + 1, 0);
+  for (long long j = 0; j < N; ++j) toff[(key[order[j]] >> 40) + 1]++;
+  for (long long t = 0; t < c->ntiles; ++t) toff[t + 1] += toff[t];
 
   CS_HIP(c, hipMalloc(&c->rec, sizeof(SampleRec) * std::max(1LL, N)));
   CS_HIP(c, hipMemcpy(c->rec, srec.data(), sizeof(SampleRec) * N, hipMemcpyHostToDevice));
-  CS_HIP(c, hipMalloc(&c->tile_off, sizeof(int) * (c->ntiles + 1)));
-  CS_HIP(c, hipMemcpy(c->tile_off, cnt.data(), sizeof(int) * (c->ntiles + 1),
-                      hipMemcpyHostToDevice));
-  CS_HIP(c, hipMalloc(&c->tile_list, sizeof(int) * std::max(1LL, nnz)));
-  if (nnz)
-    CS_HIP(c, hipMemcpy(c->tile_list, list.data(), sizeof(int) * nnz, hipMemcpyHostToDevice));
   if (dcf_dev) {
     CS_HIP(c, hipMalloc(&c->dcf_orig, sizeof(float) * N));
     CS_HIP(c, hipMemcpy(c->dcf_orig, dcf.data(), sizeof(float) * N, hipMemcpyHostToDevice));
   }
 
-  // spread work items: tiles with long lists are split into chunks whose
-  // partial tiles are summed afterwards in chunk order
-  const int chunk = 1024;
-  std::vector<int4> items, merges;
-  int nslots = 0;
+  // spread work items: each tile's samples in chunks of at most `chunk`; the
+  // slot of an item is its index in tile order, so the slots of tile t are
+  // item_off[t] .. item_off[t + 1]
+  const long long chunk = 2048;
+  std::vector<int4> items;
+  std::vector<int> ioff(c->ntiles + 1, 0);
   for (long long t = 0; t < c->ntiles; ++t) {
-    const int beg = cnt[t], end = cnt[t + 1];
-    const int len = end - beg;
-    if (len <= chunk) {
-      items.push_back(make_int4((int)t, beg, end, -1));
-    } else {
-      const int n = (len + chunk - 1) / chunk;
-      merges.push_back(make_int4((int)t, nslots, n, 0));
-      for (int q = 0; q < n; ++q)
-        items.push_back(make_int4((int)t, beg + q * chunk, std::min(end, beg + (q + 1) * chunk),
-                                  nslots + q));
-      nslots += n;
+    for (long long k = toff[t]; k < toff[t + 1]; k += chunk) {
+      const int slot = (int)items.size();
+      items.push_back(make_int4((int)t, (int)k, (int)std::min(toff[t + 1], k + chunk), slot));
     }
+    ioff[t + 1] = (int)items.size();
   }
-  // heavy items first so that the long lists start early
+  // heavy items first so that the long ones start early
   std::stable_sort(items.begin(), items.end(),
                    [](const int4& a, const int4& b) { return (a.z - a.y) > (b.z - b.y); });
   c->n_items = (long long)items.size();
-  c->n_merges = (long long)merges.size();
   CS_HIP(c, hipMalloc(&c->items, sizeof(int4) * std::max<size_t>(1, items.size())));
   if (!items.empty())
     CS_HIP(c, hipMemcpy(c->items, items.data(), sizeof(int4) * items.size(),
                         hipMemcpyHostToDevice));
-  CS_HIP(c, hipMalloc(&c->merges, sizeof(int4) * std::max<size_t>(1, merges.size())));
-  if (!merges.empty())
-    CS_HIP(c, hipMemcpy(c->merges, merges.data(), sizeof(int4) * merges.size(),
-                        hipMemcpyHostToDevice));
-  const size_t tvox = (size_t)c->tile[0] * c->tile[1] * c->tile[2];
-  CS_HIP(c, hipMalloc(&c->partial,
-                      sizeof(float2) * std::max<size_t>(1, (size_t)nslots * tvox * kCoilChunk)));
+  CS_HIP(c, hipMalloc(&c->item_off, sizeof(int) * ioff.size()));
+  CS_HIP(c, hipMemcpy(c->item_off, ioff.data(), sizeof(int) * ioff.size(),
+                      hipMemcpyHostToDevice));
+  const size_t ext = nd == 3 ? (size_t)Halo<3>::EXT : (size_t)Halo<2>::EXT;
+  c->partial_elems = std::max<size_t>(1, (size_t)c->n_items * ext * spread_max_group_elems(nd));
+  CS_HIP(c, hipMalloc(&c->partial, sizeof(float2) * c->partial_elems));
   return CS_OK;
 }
 
