@@ -162,6 +162,57 @@ typedef struct {
 int recon_run(cs_ctx* ctx, const void* y, const cs_recon_params* p,
               void* x_inout, cs_recon_stats* st);
 
+/* ---- batches of independent slices ----------------------------------------
+ * Many independent reconstructions (slices of uneven size, coil count and
+ * sketch size, each with its own context) run Algorithm 1 together.  Every
+ * outer iteration runs each slice's full-coil gradient and sketched maps,
+ * then the K inner FISTA iterations of all slices as one HIP graph that is
+ * captured at the first outer iteration (forked onto the slice streams so
+ * that slices overlap) and replayed afterwards. */
+typedef struct cs_batch cs_batch;
+
+typedef struct {
+  double alpha;                 /* step used by the slice */
+  long long n_full_applies;     /* full-coil normal applies in the loop */
+  long long n_sketch_applies;   /* sketched normal applies in the loop */
+  double wall_prep_ms;          /* host wall time of the set-up (all slices) */
+  double wall_loop_ms;          /* host wall time of the T outer iterations (all slices) */
+  long long graph_nodes;        /* nodes of the inner-iteration graph (0: eager) */
+  long long graph_replays;      /* graph launches */
+} cs_batch_stats;
+
+/* Group n contexts (host array ctxs, borrowed; each with its operator set)
+ * for batched runs on `stream` (a hipStream_t), which must differ from every
+ * slice's own stream; NULL makes the batch create (and destroy) a stream of
+ * its own.  Slices may share streams among themselves.  Errors: CS_EINVAL
+ * for a null context or a slice on the batch stream, CS_EHIP. */
+int cs_batch_create(cs_ctx* const* ctxs, int n, void* stream, cs_batch** out);
+void cs_batch_destroy(cs_batch* b);
+const char* cs_batch_last_error(const cs_batch* b);
+
+/* Algorithm 1 on every slice: y[i] device [N_i][C_i] (host array of device
+ * pointers), p[i] host params (mode CS_RECON_SKETCH, one T and K for all;
+ * lam, V, S, seed, t0, step, n_pow per slice; x_ref and reuse_b ignored),
+ * x[i] device [D_i] in/out.  use_graph = 0 issues the inner iterations
+ * eagerly (the reference for the graph path: same kernels, same results).
+ * st: host array of n (may be NULL).  Synchronous: waits for earlier work on
+ * the slice streams first and for all of its own work before returning. */
+int cs_batch_recon(cs_batch* b, const void* const* y, const cs_recon_params* p,
+                   void* const* x, int use_graph, cs_batch_stats* st);
+
+/* ---- spreading work-group shapes and their autotuner --------------------- */
+#define CS_SPREAD_NCFG 6
+/* Select spreading shape cfg in [0, CS_SPREAD_NCFG) for this context (all
+ * shapes give bit-identical results; they differ only in speed). */
+int cs_set_spread_cfg(cs_ctx* ctx, int cfg);
+/* Time a normal apply with the given maps (device [D][ncoil]) under every
+ * shape (reps applies each, HIP events on the context stream), select the
+ * fastest and report it in *best; ms (host [CS_SPREAD_NCFG], may be NULL)
+ * receives the per-apply times.  Cartesian contexts return the current
+ * shape.  Synchronous. */
+int cs_autotune_spread(cs_ctx* ctx, const void* maps, int ncoil, int reps, int* best,
+                       double* ms);
+
 /* ---- building blocks exposed for testing and benchmarking ---------------- */
 
 /* Periodized db4 wavelet prox  out = Psi^H soft(Psi v, tau)  (Sec. 2.1,

@@ -30,8 +30,10 @@ EXPORTED = [
     "cs_create", "cs_destroy", "cs_last_error", "cs_set_operator", "sense_apply",
     "sense_adjoint", "normal_apply", "sketch_build", "recon_run", "cs_prox_l1wav",
     "cs_dwt", "cs_idwt", "cs_coil_mix", "cs_dot", "cs_power_iteration", "cs_grid_shape",
-    "cs_profile_enable", "cs_profile_read",
+    "cs_profile_enable", "cs_profile_read", "cs_batch_create", "cs_batch_destroy",
+    "cs_batch_last_error", "cs_batch_recon", "cs_set_spread_cfg", "cs_autotune_spread",
 ]
+SPREAD_NCFG = 6
 NKERNELS = 12
 KERNEL_KINDS = ["fft_pass", "interp", "spread", "gather", "wavelet", "soft", "vec", "reduce",
                 "covariance", "eigensolver", "coil_mix", "spread_merge"]
@@ -89,6 +91,18 @@ class ReconStats(ctypes.Structure):
     ]
 
 
+class BatchStats(ctypes.Structure):
+    _fields_ = [
+        ("alpha", ctypes.c_double),
+        ("n_full_applies", ctypes.c_longlong),
+        ("n_sketch_applies", ctypes.c_longlong),
+        ("wall_prep_ms", ctypes.c_double),
+        ("wall_loop_ms", ctypes.c_double),
+        ("graph_nodes", ctypes.c_longlong),
+        ("graph_replays", ctypes.c_longlong),
+    ]
+
+
 _lib = None
 
 
@@ -121,9 +135,19 @@ def load() -> ctypes.CDLL:
     lib.cs_grid_shape.argtypes = [vp, vp]
     lib.cs_profile_enable.argtypes = [vp, ci]
     lib.cs_profile_read.argtypes = [vp, vp, vp]
+    lib.cs_batch_create.argtypes = [vp, ci, vp, ctypes.POINTER(vp)]
+    lib.cs_batch_destroy.argtypes = [vp]
+    lib.cs_batch_destroy.restype = None
+    lib.cs_batch_last_error.argtypes = [vp]
+    lib.cs_batch_last_error.restype = ctypes.c_char_p
+    lib.cs_batch_recon.argtypes = [vp, vp, ctypes.POINTER(ReconParams), vp, ci,
+                                   ctypes.POINTER(BatchStats)]
+    lib.cs_set_spread_cfg.argtypes = [vp, ci]
+    lib.cs_autotune_spread.argtypes = [vp, vp, ci, ci, ctypes.POINTER(ci), vp]
     for name in EXPORTED:
         f = getattr(lib, name)
-        if name not in ("cs_destroy", "cs_last_error"):
+        if name not in ("cs_destroy", "cs_last_error", "cs_batch_destroy",
+                        "cs_batch_last_error"):
             f.restype = ci
     _lib = lib
     return lib
@@ -405,3 +429,79 @@ class Context:
                                              ctypes.cast(cnt, ctypes.c_void_p)),
                     "cs_profile_read")
         return {KERNEL_KINDS[i]: (ms[i], cnt[i]) for i in range(NKERNELS)}
+
+    def set_spread_cfg(self, cfg):
+        """Select a spreading work-group shape (0 .. SPREAD_NCFG - 1)."""
+        self._check(self.lib.cs_set_spread_cfg(self._ctx, int(cfg)), "cs_set_spread_cfg")
+
+    def autotune_spread(self, maps, reps=3):
+        """Time every spreading shape on a normal apply with `maps` and keep
+        the fastest; returns (shape index, per-shape ms per apply)."""
+        ncoil = self._maps(maps)
+        best = ctypes.c_int()
+        ms = (ctypes.c_double * SPREAD_NCFG)()
+        self._check(self.lib.cs_autotune_spread(self._ctx, _ptr(maps), ncoil, int(reps),
+                                                ctypes.byref(best),
+                                                ctypes.cast(ms, ctypes.c_void_p)),
+                    "cs_autotune_spread")
+        return best.value, list(ms)
+
+
+class Batch:
+    """Independent slices (one Context each, on their own streams) run
+    Algorithm 1 together; the inner iterations of all slices form one HIP
+    graph on the batch stream (`stream`, or one the library creates)."""
+
+    def __init__(self, contexts, stream=None):
+        self.lib = load()
+        self.ctxs = list(contexts)
+        # stream None: the library creates a stream of its own for the batch
+        self.stream = stream
+        arr = (ctypes.c_void_p * len(self.ctxs))(*[c._ctx.value for c in self.ctxs])
+        self._b = ctypes.c_void_p()
+        rc = self.lib.cs_batch_create(arr, len(self.ctxs),
+                                      None if stream is None
+                                      else ctypes.c_void_p(stream.cuda_stream),
+                                      ctypes.byref(self._b))
+        if rc != 0:
+            raise CSError(f"cs_batch_create failed ({rc})")
+
+    def recon(self, ys, xs, lam, T, K, V, S, seed, t0=1, step=None, n_pow=30,
+              use_graph=True):
+        """Run Algorithm 1 on every slice: ys[i] data, xs[i] image (in/out);
+        lam, V, S, seed, step may be per-slice sequences.  Returns one dict of
+        statistics per slice."""
+        n = len(self.ctxs)
+        per = lambda v: list(v) if isinstance(v, (list, tuple)) else [v] * n
+        lam, V, S, seed = per(lam), per(V), per(S), per(seed)
+        step = per(0.0 if step is None else step)
+        P = (ReconParams * n)()
+        for i, c in enumerate(self.ctxs):
+            c._data(ys[i], c.C)
+            c._img(xs[i], "x")
+            P[i].mode = CS_RECON_SKETCH
+            P[i].lam = float(lam[i])
+            P[i].T, P[i].K, P[i].V, P[i].S = int(T), int(K), int(V[i]), int(S[i])
+            P[i].seed = int(seed[i])
+            P[i].t0 = int(t0)
+            P[i].step = float(step[i])
+            P[i].n_pow = int(n_pow)
+        yp = (ctypes.c_void_p * n)(*[y.data_ptr() for y in ys])
+        xp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        st = (BatchStats * n)()
+        rc = self.lib.cs_batch_recon(self._b, yp, P, xp, int(bool(use_graph)), st)
+        if rc != 0:
+            raise CSError(f"cs_batch_recon failed ({rc}): "
+                          f"{self.lib.cs_batch_last_error(self._b).decode()}")
+        return [{f: getattr(s, f) for f, _ in BatchStats._fields_} for s in st]
+
+    def close(self):
+        if getattr(self, "_b", None) and self._b.value:
+            self.lib.cs_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -4,6 +4,7 @@
 // (Sec. 2.3.4, Sec. 3.3.1).
 #include <cmath>
 #include <cstring>
+#include <functional>
 
 #include "cs_internal.h"
 
@@ -467,6 +468,12 @@ int create_impl(const cs_geom* g, void* stream, cs_ctx** out) {
   return CS_OK;
 }
 
+}  // namespace
+
+int adjoint_all(cs_ctx* c, const float2* maps, int ncoil, const float2* y, float2* x) {
+  return chunk_loop(c, ncoil, op_adjoint, maps, y, x);
+}
+
 int power_iter(cs_ctx* c, const float2* maps, int ncoil, int n_iter, double* L) {
   float2* v = c->img[8];
   float2* w = c->img[9];
@@ -524,12 +531,46 @@ int sketch_impl(cs_ctx* c, const float2* y, int V, int S, uint64_t seed, int t, 
   return CS_OK;
 }
 
-}  // namespace
-
 int op_normal(cs_ctx* c, const float2* maps, int ncoil, const float2* x, float2* out) {
   for (int c0 = 0; c0 < ncoil; c0 += kCoilChunk) {
     const int cb = std::min(kCoilChunk, ncoil - c0);
     CS_TRY(op_normal_chunk(c, maps, ncoil, c0, cb, x, out));
+  }
+  return CS_OK;
+}
+
+// K FISTA iterations on the sketched subproblem of Algorithm 1,
+//   min_x 1/2 ||A_S (x - x^t)||^2 + <x, d> + lambda ||Psi x||_1,
+// started at x^t = x with the momentum restarted: gradient A_S^H A_S (z - x^t)
+// + d, step a, prox threshold tau_l = a lambda.  d is c->img[1]; c->smaps
+// holds the Ch sketched maps.  Only kernels on the context stream, no host
+// synchronisation (the sequence can be captured in a graph).  `timed`, when
+// given, wraps the sketched apply (kind 1) and the prox (kind 2).
+int inner_fista(cs_ctx* c, float2* x, int Ch, int K, float a, float tau_l,
+                const std::function<int(int, const std::function<int()>&)>* timed) {
+  const long long D = c->D;
+  float2* d = c->img[1];
+  float2* z = c->img[2];
+  float2* xt = c->img[3];
+  float2* e = c->img[4];
+  float2* g = c->img[5];
+  float2* v = c->img[6];
+  float2* xn = c->img[7];
+  auto run = [&](int kind, const std::function<int()>& fn) {
+    return timed ? (*timed)(kind, fn) : fn();
+  };
+  CS_TRY(vec_copy(c, xt, x, D));
+  CS_TRY(vec_copy(c, z, x, D));
+  double tau = 1.0;
+  for (int k = 0; k < K; ++k) {
+    CS_TRY(vec_axpby(c, e, 1.f, z, -1.f, xt, D));
+    CS_TRY(run(1, [&] { return op_normal(c, c->smaps, Ch, e, g); }));
+    CS_TRY(vec_fista_step(c, v, z, a, g, 1.f, d, D));
+    CS_TRY(run(2, [&] { return prox_l1(c, v, tau_l, xn); }));
+    const double tn = (1.0 + std::sqrt(1.0 + 4.0 * tau * tau)) / 2.0;
+    const float beta = (float)((tau - 1.0) / tn);
+    tau = tn;
+    CS_TRY(vec_momentum(c, z, x, xn, beta, D));
   }
   return CS_OK;
 }
@@ -725,8 +766,6 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
   float2* b = c->img[0];
   float2* d = c->img[1];
   float2* z = c->img[2];
-  float2* xt = c->img[3];
-  float2* e = c->img[4];
   float2* g = c->img[5];
   float2* v = c->img[6];
   float2* xn = c->img[7];
@@ -804,6 +843,8 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
     phases.push_back(ph);
     return r;
   };
+  const std::function<int(int, const std::function<int()>&)> timed_fn =
+      [&](int kind, const std::function<int()>& fn) { return timed(kind, fn); };
   CS_HIP(c, hipEventRecord(ev0, c->stream));
   int rc = CS_OK;
   auto record = [&](int it) -> int {
@@ -846,21 +887,9 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
           return sketch_impl(c, y, p->V, p->S, p->seed, t, 0, c->smaps, nullptr);
         }));
       // K FISTA steps on 1/2||A_S(x - x^t)||^2 + <x, d> + g(x), momentum restarted
-      CS_TRY(vec_copy(c, xt, x, D));
-      CS_TRY(vec_copy(c, z, x, D));
-      double tau = 1.0;
-      for (int k = 0; k < p->K; ++k) {
-        CS_TRY(vec_axpby(c, e, 1.f, z, -1.f, xt, D));
-        CS_TRY(timed(1, [&] { return op_normal(c, c->smaps, Ch, e, g); }));
-        ++nsk;
-        CS_TRY(vec_fista_step(c, v, z, a, g, 1.f, d, D));
-        CS_TRY(timed(2, [&] { return prox_l1(c, v, tau_l, xn); }));
-        ++nprox;
-        const double tn = (1.0 + std::sqrt(1.0 + 4.0 * tau * tau)) / 2.0;
-        const float beta = (float)((tau - 1.0) / tn);
-        tau = tn;
-        CS_TRY(vec_momentum(c, z, x, xn, beta, D));
-      }
+      CS_TRY(inner_fista(c, x, Ch, p->K, a, tau_l, &timed_fn));
+      nsk += p->K;
+      nprox += p->K;
       CS_TRY(record(it));
     }
   }

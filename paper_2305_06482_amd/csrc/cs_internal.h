@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <map>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -227,8 +228,14 @@ int coil_mix(cs_ctx* c, const float2* in, int in_ldc, int in_c0, int cin,
              const double* M, int cout, float2* out, int out_ldc, int out_c0,
              float out_scale);
 
-// operators (api.cpp)
+// operators and solver pieces (api.hip)
 int op_normal(cs_ctx* c, const float2* maps, int ncoil, const float2* x,
               float2* out);
+int adjoint_all(cs_ctx* c, const float2* maps, int ncoil, const float2* y, float2* x);
+int power_iter(cs_ctx* c, const float2* maps, int ncoil, int n_iter, double* L);
+int sketch_impl(cs_ctx* c, const float2* y, int V, int S, uint64_t seed, int t, int refresh,
+                float2* smaps, std::vector<int8_t>* signs_out);
+int inner_fista(cs_ctx* c, float2* x, int Ch, int K, float a, float tau_l,
+                const std::function<int(int, const std::function<int()>&)>* timed);
 
 }  // namespace cs
