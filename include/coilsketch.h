@@ -120,7 +120,9 @@ int sketch_build(cs_ctx* ctx, const void* y, int V, int S, uint64_t seed, int t,
                  int8_t* signs);
 
 /* Recon modes */
-enum { CS_RECON_FULL = 0, CS_RECON_SKETCH = 1 };
+enum { CS_RECON_FULL = 0, CS_RECON_SKETCH = 1, CS_RECON_SKETCH_LEARNED = 2 };
+
+typedef struct cs_cnn cs_cnn;
 
 typedef struct {
   int mode;          /* CS_RECON_FULL: plain FISTA; CS_RECON_SKETCH: Algorithm 1 */
@@ -135,6 +137,7 @@ typedef struct {
   int n_pow;         /* power-iteration count (default 30) */
   int reuse_b;       /* non-zero: reuse b = A^H y from the previous call */
   const void* x_ref; /* device [D] or NULL: per-iteration distance reference */
+  cs_cnn* cnn;       /* CS_RECON_SKETCH_LEARNED: the warm-start network (borrowed) */
 } cs_recon_params;
 
 typedef struct {
@@ -154,13 +157,54 @@ typedef struct {
   /* GPU time before the first iteration: b = A^H y (unless reused), the PCA
    * basis and first sketch (SKETCH), and the power iteration (step <= 0) */
   double prep_ms;
+  /* SKETCH_LEARNED: outer iterations whose warm start was accepted / fell
+   * back to the plain start, and the GPU time of the warm-start decisions */
+  long long n_warm_accepted, n_warm_rejected;
+  double ms_warm;
 } cs_recon_stats;
 
 /* Reconstruction (Algorithm 1 or plain FISTA) of x from data y on the
  * operator bound by cs_set_operator.  y device [N][C]; x_inout device [D]:
- * x^{t0} on entry, the result on exit.  Synchronous. */
+ * x^{t0} on entry, the result on exit.  CS_RECON_SKETCH_LEARNED runs
+ * Algorithm 1 with each subproblem's FISTA started at
+ * z0 = x^t + s_o CNN(x^t / s_x, d^t / s_d) (s_d = rms(d^t), s_o = alpha s_d,
+ * s_x = rms(x^t) or s_o while x^t = 0) when the FP64 subproblem objective
+ * at z0 is no larger than at x^t, else at x^t (the fallback); the
+ * subproblems, hence the method's fixed point, are unchanged.  Synchronous. */
 int recon_run(cs_ctx* ctx, const void* y, const cs_recon_params* p,
               void* x_inout, cs_recon_stats* st);
+
+/* ---- learned warm start (no counterpart in the paper) ------------------------
+ * A residual 3D CNN, 4 -> 16 -> 32 -> 64 -> 2 channels, 3x3x3 convolutions
+ * (zero padding) with ReLU after the first three, on BF16 MFMA with FP32
+ * accumulation; parameters and Adam moments FP32.  Volumes are channel-last
+ * FP32: inputs [nz][ny][nx][4] = (re x / s_x, im x / s_x, re d / s_d,
+ * im d / s_d), outputs and targets [nz][ny][nx][2] = Delta / s_o.  Calls run
+ * on the network's stream; buffers grow on demand (the only allocations). */
+int cs_cnn_create(void* stream, uint64_t seed, cs_cnn** out);
+void cs_cnn_destroy(cs_cnn* n);
+const char* cs_cnn_last_error(const cs_cnn* n);
+/* parameter count; layout per layer: W [27][cin][cout] (tap = (dz 3 + dy) 3 +
+ * dx, offsets d - 1) then b [cout] */
+long long cs_cnn_num_params(const cs_cnn* n);
+/* host copies of the parameters and/or of the last computed gradient */
+int cs_cnn_get_params(cs_cnn* n, float* host, float* grad_host);
+int cs_cnn_set_params(cs_cnn* n, const float* host);
+/* out = CNN(in): in device [V][4], out device [V][2] */
+int cs_cnn_forward(cs_cnn* n, const float* in, int nz, int ny, int nx, float* out);
+/* mean over voxels of the squared error summed over the 2 channels, and its
+ * gradient (kept for cs_cnn_get_params).  Synchronous. */
+int cs_cnn_loss_grad(cs_cnn* n, const float* in, const float* target, int nz, int ny, int nx,
+                     double* loss);
+/* cs_cnn_loss_grad then one Adam step (beta 0.9, 0.999, eps 1e-8) */
+int cs_cnn_train_step(cs_cnn* n, const float* in, const float* target, int nz, int ny, int nx,
+                      float lr, double* loss);
+/* Training pairs from the sketched solver itself: runs T outer iterations of
+ * Algorithm 1 (mode CS_RECON_SKETCH parameters) from x_inout and writes, for
+ * outer iteration t, the packed input at inputs + t D 4 and the target
+ * (x^{t+1} - x^t) / s_o at targets + t D 2 (device FP32).  Synchronous. */
+int cs_cnn_collect(cs_ctx* ctx, const void* y, const cs_recon_params* p, void* x_inout,
+                   float* inputs, float* targets);
 
 /* ---- batches of independent slices ----------------------------------------
  * Many independent reconstructions (slices of uneven size, coil count and

@@ -3,6 +3,6 @@
 ``binding.Context`` is the Python entry point; it loads ``libcoilsketch.so``
 (built by ``build.build()``) and forwards tensors' device pointers to it.
 """
-from .binding import Batch, CSError, Context, load  # noqa: F401
+from .binding import CNN, Batch, CSError, Context, load  # noqa: F401
 
-__all__ = ["Batch", "Context", "CSError", "load"]
+__all__ = ["Batch", "CNN", "Context", "CSError", "load"]

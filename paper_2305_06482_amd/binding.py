@@ -25,6 +25,7 @@ CS_CART = 0
 CS_NONCART = 1
 CS_RECON_FULL = 0
 CS_RECON_SKETCH = 1
+CS_RECON_SKETCH_LEARNED = 2
 
 EXPORTED = [
     "cs_create", "cs_destroy", "cs_last_error", "cs_set_operator", "sense_apply",
@@ -32,6 +33,9 @@ EXPORTED = [
     "cs_dwt", "cs_idwt", "cs_coil_mix", "cs_dot", "cs_power_iteration", "cs_grid_shape",
     "cs_profile_enable", "cs_profile_read", "cs_batch_create", "cs_batch_destroy",
     "cs_batch_last_error", "cs_batch_recon", "cs_set_spread_cfg", "cs_autotune_spread",
+    "cs_cnn_create", "cs_cnn_destroy", "cs_cnn_last_error", "cs_cnn_num_params",
+    "cs_cnn_get_params", "cs_cnn_set_params", "cs_cnn_forward", "cs_cnn_loss_grad",
+    "cs_cnn_train_step", "cs_cnn_collect",
 ]
 SPREAD_NCFG = 6
 NKERNELS = 12
@@ -71,6 +75,7 @@ class ReconParams(ctypes.Structure):
         ("n_pow", ctypes.c_int),
         ("reuse_b", ctypes.c_int),
         ("x_ref", ctypes.c_void_p),
+        ("cnn", ctypes.c_void_p),
     ]
 
 
@@ -88,6 +93,9 @@ class ReconStats(ctypes.Structure):
         ("ms_prox", ctypes.c_double),
         ("ms_sketch", ctypes.c_double),
         ("prep_ms", ctypes.c_double),
+        ("n_warm_accepted", ctypes.c_longlong),
+        ("n_warm_rejected", ctypes.c_longlong),
+        ("ms_warm", ctypes.c_double),
     ]
 
 
@@ -144,11 +152,25 @@ def load() -> ctypes.CDLL:
                                    ctypes.POINTER(BatchStats)]
     lib.cs_set_spread_cfg.argtypes = [vp, ci]
     lib.cs_autotune_spread.argtypes = [vp, vp, ci, ci, ctypes.POINTER(ci), vp]
+    lib.cs_cnn_create.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(vp)]
+    lib.cs_cnn_destroy.argtypes = [vp]
+    lib.cs_cnn_destroy.restype = None
+    lib.cs_cnn_last_error.argtypes = [vp]
+    lib.cs_cnn_last_error.restype = ctypes.c_char_p
+    lib.cs_cnn_num_params.argtypes = [vp]
+    lib.cs_cnn_get_params.argtypes = [vp, vp, vp]
+    lib.cs_cnn_set_params.argtypes = [vp, vp]
+    lib.cs_cnn_forward.argtypes = [vp, vp, ci, ci, ci, vp]
+    lib.cs_cnn_loss_grad.argtypes = [vp, vp, vp, ci, ci, ci, ctypes.POINTER(cd)]
+    lib.cs_cnn_train_step.argtypes = [vp, vp, vp, ci, ci, ci, cf, ctypes.POINTER(cd)]
+    lib.cs_cnn_collect.argtypes = [vp, vp, ctypes.POINTER(ReconParams), vp, vp, vp]
     for name in EXPORTED:
         f = getattr(lib, name)
         if name not in ("cs_destroy", "cs_last_error", "cs_batch_destroy",
-                        "cs_batch_last_error"):
+                        "cs_batch_last_error", "cs_cnn_destroy", "cs_cnn_last_error",
+                        "cs_cnn_num_params"):
             f.restype = ci
+    lib.cs_cnn_num_params.restype = ctypes.c_longlong
     _lib = lib
     return lib
 
@@ -183,6 +205,9 @@ class ReconResult:
     ms_prox: float = 0.0
     ms_sketch: float = 0.0
     prep_ms: float = 0.0
+    n_warm_accepted: int = 0
+    n_warm_rejected: int = 0
+    ms_warm: float = 0.0
     time_ms: list = field(default_factory=list)
     dist: list = field(default_factory=list)
 
@@ -328,7 +353,7 @@ class Context:
         return smaps, lam, Uc, sg
 
     def recon_run(self, y, mode="sketch", lam=1e-3, T=10, K=5, V=2, S=2, seed=0, t0=1,
-                  step=0.0, n_pow=30, reuse_b=False, x=None, x_ref=None):
+                  step=0.0, n_pow=30, reuse_b=False, x=None, x_ref=None, cnn=None):
         self._data(y, self.C)
         if x is None:
             x = torch.zeros(self.shape, dtype=torch.complex64, device=self.device)
@@ -336,7 +361,9 @@ class Context:
         if x_ref is not None:
             self._img(x_ref, "x_ref")
         p = ReconParams()
-        p.mode = CS_RECON_SKETCH if mode == "sketch" else CS_RECON_FULL
+        p.mode = {"sketch": CS_RECON_SKETCH, "full": CS_RECON_FULL,
+                  "learned": CS_RECON_SKETCH_LEARNED}[mode]
+        p.cnn = None if cnn is None else cnn._n.value
         p.lam = float(lam)
         p.T, p.K, p.V, p.S = int(T), int(K), int(V), int(S)
         p.seed = int(seed)
@@ -358,6 +385,8 @@ class Context:
                            total_ms=st.total_ms, ms_full_normal=st.ms_full_normal,
                            ms_sketch_normal=st.ms_sketch_normal, ms_prox=st.ms_prox,
                            ms_sketch=st.ms_sketch, prep_ms=st.prep_ms,
+                           n_warm_accepted=st.n_warm_accepted,
+                           n_warm_rejected=st.n_warm_rejected, ms_warm=st.ms_warm,
                            time_ms=list(tms[:T]),
                            dist=list(dist[:T]) if x_ref is not None else [])
 
@@ -430,6 +459,29 @@ class Context:
                     "cs_profile_read")
         return {KERNEL_KINDS[i]: (ms[i], cnt[i]) for i in range(NKERNELS)}
 
+    def collect(self, y, T, K, V, S, seed, lam, t0=1, step=0.0, n_pow=30, x=None):
+        """Training pairs from T outer iterations of Algorithm 1: returns
+        (inputs [T, *shape, 4], targets [T, *shape, 2]) as float32 tensors
+        (2D images get a unit z axis), and the final iterate."""
+        self._data(y, self.C)
+        if x is None:
+            x = torch.zeros(self.shape, dtype=torch.complex64, device=self.device)
+        self._img(x, "x")
+        vol = self.shape if self.ndim == 3 else (1,) + self.shape
+        inp = torch.empty((T,) + vol + (4,), dtype=torch.float32, device=self.device)
+        tgt = torch.empty((T,) + vol + (2,), dtype=torch.float32, device=self.device)
+        p = ReconParams()
+        p.mode = CS_RECON_SKETCH
+        p.lam = float(lam)
+        p.T, p.K, p.V, p.S = int(T), int(K), int(V), int(S)
+        p.seed = int(seed)
+        p.t0 = int(t0)
+        p.step = float(step)
+        p.n_pow = int(n_pow)
+        self._check(self.lib.cs_cnn_collect(self._ctx, _ptr(y), ctypes.byref(p), _ptr(x),
+                                            _ptr(inp), _ptr(tgt)), "cs_cnn_collect")
+        return inp, tgt, x
+
     def set_spread_cfg(self, cfg):
         """Select a spreading work-group shape (0 .. SPREAD_NCFG - 1)."""
         self._check(self.lib.cs_set_spread_cfg(self._ctx, int(cfg)), "cs_set_spread_cfg")
@@ -445,6 +497,89 @@ class Context:
                                                 ctypes.cast(ms, ctypes.c_void_p)),
                     "cs_autotune_spread")
         return best.value, list(ms)
+
+
+class CNN:
+    """The learned warm-start network (parameters on the device)."""
+
+    def __init__(self, seed=0, stream=None):
+        self.lib = load()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._n = ctypes.c_void_p()
+        rc = self.lib.cs_cnn_create(ctypes.c_void_p(self.stream.cuda_stream),
+                                    ctypes.c_uint64(int(seed)), ctypes.byref(self._n))
+        if rc != 0:
+            raise CSError(f"cs_cnn_create failed ({rc})")
+
+    def _check(self, rc, what):
+        if rc != 0:
+            raise CSError(f"{what} failed ({rc}): {self.lib.cs_cnn_last_error(self._n).decode()}")
+
+    @property
+    def num_params(self):
+        return int(self.lib.cs_cnn_num_params(self._n))
+
+    def get_params(self):
+        import numpy as np
+        p = np.empty(self.num_params, dtype=np.float32)
+        self._check(self.lib.cs_cnn_get_params(self._n, p.ctypes.data, None), "get_params")
+        return p
+
+    def get_grads(self):
+        import numpy as np
+        g = np.empty(self.num_params, dtype=np.float32)
+        self._check(self.lib.cs_cnn_get_params(self._n, None, g.ctypes.data), "get_grads")
+        return g
+
+    def set_params(self, p):
+        import numpy as np
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        if p.size != self.num_params:
+            raise ValueError("parameter count")
+        self._check(self.lib.cs_cnn_set_params(self._n, p.ctypes.data), "set_params")
+
+    @staticmethod
+    def _vol(t, ch, name):
+        _need(t, torch.float32, None, name)
+        if t.dim() != 4 or t.shape[-1] != ch:
+            raise ValueError(f"{name} must be [nz, ny, nx, {ch}]")
+        return t.shape[0], t.shape[1], t.shape[2]
+
+    def forward(self, inp):
+        nz, ny, nx = self._vol(inp, 4, "inp")
+        out = torch.empty((nz, ny, nx, 2), dtype=torch.float32, device=inp.device)
+        self._check(self.lib.cs_cnn_forward(self._n, _ptr(inp), nz, ny, nx, _ptr(out)), "forward")
+        return out
+
+    def loss_grad(self, inp, target):
+        nz, ny, nx = self._vol(inp, 4, "inp")
+        if tuple(self._vol(target, 2, "target")) != (nz, ny, nx):
+            raise ValueError("target shape")
+        loss = ctypes.c_double()
+        self._check(self.lib.cs_cnn_loss_grad(self._n, _ptr(inp), _ptr(target), nz, ny, nx,
+                                              ctypes.byref(loss)), "loss_grad")
+        return loss.value
+
+    def train_step(self, inp, target, lr):
+        nz, ny, nx = self._vol(inp, 4, "inp")
+        if tuple(self._vol(target, 2, "target")) != (nz, ny, nx):
+            raise ValueError("target shape")
+        loss = ctypes.c_double()
+        self._check(self.lib.cs_cnn_train_step(self._n, _ptr(inp), _ptr(target), nz, ny, nx,
+                                               ctypes.c_float(lr), ctypes.byref(loss)),
+                    "train_step")
+        return loss.value
+
+    def close(self):
+        if getattr(self, "_n", None) and self._n.value:
+            self.lib.cs_cnn_destroy(self._n)
+            self._n = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:

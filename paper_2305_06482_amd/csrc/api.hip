@@ -545,9 +545,11 @@ int op_normal(cs_ctx* c, const float2* maps, int ncoil, const float2* x, float2*
 // + d, step a, prox threshold tau_l = a lambda.  d is c->img[1]; c->smaps
 // holds the Ch sketched maps.  Only kernels on the context stream, no host
 // synchronisation (the sequence can be captured in a graph).  `timed`, when
-// given, wraps the sketched apply (kind 1) and the prox (kind 2).
+// given, wraps the sketched apply (kind 1) and the prox (kind 2); `start`,
+// when given, is the first iterate instead of x^t.
 int inner_fista(cs_ctx* c, float2* x, int Ch, int K, float a, float tau_l,
-                const std::function<int(int, const std::function<int()>&)>* timed) {
+                const std::function<int(int, const std::function<int()>&)>* timed,
+                const float2* start) {
   const long long D = c->D;
   float2* d = c->img[1];
   float2* z = c->img[2];
@@ -560,6 +562,7 @@ int inner_fista(cs_ctx* c, float2* x, int Ch, int K, float a, float tau_l,
     return timed ? (*timed)(kind, fn) : fn();
   };
   CS_TRY(vec_copy(c, xt, x, D));
+  if (start) CS_TRY(vec_copy(c, x, start, D));  // warm start; the subproblem stays at x^t
   CS_TRY(vec_copy(c, z, x, D));
   double tau = 1.0;
   for (int k = 0; k < K; ++k) {
@@ -750,15 +753,78 @@ int cs_profile_read(cs_ctx* c, double* ms, long long* count) {
   return CS_OK;
 }
 
+}  // extern "C"
+
+namespace cs {
+// Scales of the network's inputs and output: s_d = rms(d); s_o = alpha rms(d),
+// the size of one gradient step, which is the unit of the predicted change;
+// s_x = rms(x), or s_o while x = 0.  A vanishing scale is replaced by 1.
+int warm_scales(cs_ctx* c, const float2* x, const float2* d, double alpha, double* sx,
+                double* sd, double* so) {
+  double xx[2], dd[2];
+  CS_TRY(vec_dot(c, x, x, c->D, xx));
+  CS_TRY(vec_dot(c, d, d, c->D, dd));
+  const double rx = std::sqrt(xx[0] / (double)c->D), rd = std::sqrt(dd[0] / (double)c->D);
+  *sd = rd > 0 ? rd : 1.0;
+  *so = alpha * rd > 0 ? alpha * rd : 1.0;
+  *sx = rx > 0 ? rx : *so;
+  return CS_OK;
+}
+}  // namespace cs
+
+extern "C" {
+
+int cs_cnn_collect(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout,
+                   float* inputs, float* targets) {
+  if (!c) return CS_EINVAL;
+  if (!c->have_op) return fail(c, CS_EINVAL, "cs_set_operator has not been called");
+  if (!y_ || !p || !x_inout || !inputs || !targets) return fail(c, CS_EINVAL, "null argument");
+  if (p->T < 1 || p->K < 1) return fail(c, CS_EINVAL, "iteration counts");
+  const float2* y = (const float2*)y_;
+  float2* x = (float2*)x_inout;
+  const long long D = c->D;
+  float2* b = c->img[0];
+  float2* d = c->img[1];
+  float2* g = c->img[5];
+  float2* xo = c->img[8];
+  const int Ch = p->V + p->S;
+  CS_TRY(adjoint_all(c, c->maps, c->C, y, b));
+  c->have_b = true;
+  CS_TRY(sketch_impl(c, y, p->V, p->S, p->seed, p->t0, 0, c->smaps, nullptr));
+  double alpha = p->step;
+  if (alpha <= 0) {
+    double L = 0;
+    CS_TRY(power_iter(c, c->smaps, Ch, p->n_pow > 0 ? p->n_pow : 30, &L));
+    alpha = 1.0 / L;
+  }
+  for (int it = 0; it < p->T; ++it) {
+    CS_TRY(op_normal(c, c->maps, c->C, x, g));
+    CS_TRY(vec_axpby(c, d, 1.f, g, -1.f, b, D));
+    if (it > 0) CS_TRY(sketch_impl(c, y, p->V, p->S, p->seed, p->t0 + it, 0, c->smaps, nullptr));
+    double sx, sd, so;
+    CS_TRY(warm_scales(c, x, d, alpha, &sx, &sd, &so));
+    CS_TRY(cnn_pack_input(c, x, d, (float)sx, (float)sd, inputs + (size_t)it * D * 4));
+    CS_TRY(vec_copy(c, xo, x, D));
+    CS_TRY(inner_fista(c, x, Ch, p->K, (float)alpha, (float)(alpha * p->lam), nullptr, nullptr));
+    CS_TRY(cnn_pack_target(c, x, xo, (float)so, targets + (size_t)it * D * 2));
+  }
+  CS_HIP(c, hipStreamSynchronize(c->stream));
+  return CS_OK;
+}
+
 int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout,
               cs_recon_stats* st) {
   if (!c) return CS_EINVAL;
   if (!c->have_op) return fail(c, CS_EINVAL, "cs_set_operator has not been called");
   if (!y_ || !p || !x_inout) return fail(c, CS_EINVAL, "null argument");
-  if (p->mode != CS_RECON_FULL && p->mode != CS_RECON_SKETCH)
+  if (p->mode != CS_RECON_FULL && p->mode != CS_RECON_SKETCH &&
+      p->mode != CS_RECON_SKETCH_LEARNED)
     return fail(c, CS_EINVAL, "recon mode");
-  if (p->T < 0 || (p->mode == CS_RECON_SKETCH && p->K < 1))
+  const bool learned = p->mode == CS_RECON_SKETCH_LEARNED;
+  if (learned && !p->cnn) return fail(c, CS_EINVAL, "learned mode needs a network");
+  if (p->T < 0 || (p->mode != CS_RECON_FULL && p->K < 1))
     return fail(c, CS_EINVAL, "iteration counts");
+  if (st) st->n_warm_accepted = st->n_warm_rejected = 0;
   const float2* y = (const float2*)y_;
   float2* x = (float2*)x_inout;
   const long long D = c->D;
@@ -789,7 +855,7 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
   const int n_pow = p->n_pow > 0 ? p->n_pow : 30;
   long long nfull = 0, nsk = 0, nprox = 0;
   double alpha = p->step;
-  if (p->mode == CS_RECON_SKETCH) {
+  if (p->mode != CS_RECON_FULL) {
     CS_TRY(sketch_impl(c, y, p->V, p->S, p->seed, p->t0, 0, c->smaps, nullptr));
     if (alpha <= 0) {
       double L = 0;
@@ -875,6 +941,40 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
       CS_TRY(record(it));
     }
   } else {
+    // learned warm start: z0 = x^t + s_o CNN(x^t / s_x, d^t / s_d) is used
+    // as the first inner iterate only when the FP64 subproblem objective
+    //   phi(u) = 1/2 <u - x^t, A_S^H A_S (u - x^t)> + Re<u, d> + lam ||Psi u||_1
+    // at z0 is no larger than at x^t; otherwise the plain start is kept
+    long long n_acc = 0, n_rej = 0;
+    auto learned_start = [&](const float2*& warm) -> int {
+      double sx, sd, so;
+      CS_TRY(warm_scales(c, x, d, alpha, &sx, &sd, &so));
+      float2* z0 = c->img[8];
+      float2* e = c->img[9];
+      float2* coef = c->img[6];
+      CS_TRY(cnn_warm_start(p->cnn, c, x, d, (float)sx, (float)sd, (float)so, z0));
+      CS_TRY(vec_axpby(c, e, 1.f, z0, -1.f, x, D));
+      CS_TRY(op_normal(c, c->smaps, Ch, e, g));
+      ++nsk;
+      double q[2], lz[2], lx[2], l1z = 0, l1x = 0;
+      CS_TRY(vec_dot(c, e, g, D, q));
+      CS_TRY(vec_dot(c, z0, d, D, lz));
+      CS_TRY(vec_dot(c, x, d, D, lx));
+      CS_TRY(dwt_fwd(c, z0, coef));
+      CS_TRY(vec_abs_sum(c, coef, D, &l1z));
+      CS_TRY(dwt_fwd(c, x, coef));
+      CS_TRY(vec_abs_sum(c, coef, D, &l1x));
+      const double phz = 0.5 * q[0] + lz[0] + p->lam * l1z;
+      const double phx = lx[0] + p->lam * l1x;
+      if (std::isfinite(phz) && phz <= phx) {
+        warm = z0;
+        ++n_acc;
+      } else {
+        warm = nullptr;
+        ++n_rej;
+      }
+      return CS_OK;
+    };
     for (int it = 0; it < p->T; ++it) {
       const int t = p->t0 + it;
       // true gradient d = A^H (A x^t - y) = A^H A x^t - b (Alg. 1 line 9)
@@ -886,11 +986,17 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
         CS_TRY(timed(3, [&] {
           return sketch_impl(c, y, p->V, p->S, p->seed, t, 0, c->smaps, nullptr);
         }));
+      const float2* warm = nullptr;
+      if (learned) CS_TRY(timed(4, [&] { return learned_start(warm); }));
       // K FISTA steps on 1/2||A_S(x - x^t)||^2 + <x, d> + g(x), momentum restarted
-      CS_TRY(inner_fista(c, x, Ch, p->K, a, tau_l, &timed_fn));
+      CS_TRY(inner_fista(c, x, Ch, p->K, a, tau_l, &timed_fn, warm));
       nsk += p->K;
       nprox += p->K;
       CS_TRY(record(it));
+    }
+    if (st) {
+      st->n_warm_accepted = n_acc;
+      st->n_warm_rejected = n_rej;
     }
   }
   CS_HIP(c, hipEventRecord(ev_end, c->stream));
@@ -915,7 +1021,7 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
     st->n_prox = nprox;
     st->total_ms = total - excluded;
     st->prep_ms = prep;
-    double pms[4] = {0, 0, 0, 0};
+    double pms[5] = {0, 0, 0, 0, 0};
     for (auto& ph : phases) {
       float ms = 0.f;
       CS_HIP(c, hipEventElapsedTime(&ms, ph.a, ph.b));
@@ -925,6 +1031,7 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
     st->ms_sketch_normal = pms[1];
     st->ms_prox = pms[2];
     st->ms_sketch = pms[3];
+    st->ms_warm = pms[4];
   }
   double chk[2];
   CS_TRY(vec_dot(c, x, x, D, chk));

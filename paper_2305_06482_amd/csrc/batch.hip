@@ -185,7 +185,7 @@ int cs_batch_recon(cs_batch* b, const void* const* y, const cs_recon_params* p,
     if (!use_graph) {
       for (int i = 0; i < n; ++i) {
         int rc = inner_fista(b->ctx[i], (float2*)x[i], p[i].V + p[i].S, K, a[i], tau_l[i],
-                             nullptr);
+                             nullptr, nullptr);
         if (rc) return slice_fail(b, i, rc);
       }
       continue;
@@ -198,7 +198,7 @@ int cs_batch_recon(cs_batch* b, const void* const* y, const cs_recon_params* p,
       int rc = fork_from_main(b);
       for (int i = 0; i < n && rc == CS_OK; ++i) {
         rc = inner_fista(b->ctx[i], (float2*)x[i], p[i].V + p[i].S, K, a[i], tau_l[i],
-                         nullptr);
+                         nullptr, nullptr);
         if (rc) rc = slice_fail(b, i, rc);
       }
       if (rc == CS_OK) rc = join_to_main(b);

@@ -215,6 +215,7 @@ int vec_momentum(cs_ctx* c, float2* z, float2* x, const float2* xn, float beta,
                  long long n);
 int vec_dist(cs_ctx* c, const float2* a, const float2* b, long long n,
              double* num, double* den);
+int vec_abs_sum(cs_ctx* c, const float2* a, long long n, double* out);
 
 // wavelet.hip
 int wavelet_init(cs_ctx* c);
@@ -236,6 +237,16 @@ int power_iter(cs_ctx* c, const float2* maps, int ncoil, int n_iter, double* L);
 int sketch_impl(cs_ctx* c, const float2* y, int V, int S, uint64_t seed, int t, int refresh,
                 float2* smaps, std::vector<int8_t>* signs_out);
 int inner_fista(cs_ctx* c, float2* x, int Ch, int K, float a, float tau_l,
-                const std::function<int(int, const std::function<int()>&)>* timed);
+                const std::function<int(int, const std::function<int()>&)>* timed,
+                const float2* start);
+
+// cnn.hip: learned warm start
+int cnn_pack_input(cs_ctx* c, const float2* x, const float2* d, float sx, float sd,
+                   float* out);
+int cnn_pack_target(cs_ctx* c, const float2* xn, const float2* xo, float so, float* out);
+int cnn_warm_start(cs_cnn* n, cs_ctx* c, const float2* x, const float2* d, float sx, float sd,
+                   float so, float2* z0);
+int warm_scales(cs_ctx* c, const float2* x, const float2* d, double alpha, double* sx,
+                double* sd, double* so);
 
 }  // namespace cs

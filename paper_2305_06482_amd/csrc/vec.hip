@@ -6,6 +6,8 @@
 // Reductions accumulate in FP64: every block sums a fixed contiguous range in
 // a fixed tree order, and a single block then sums the block partials in
 // index order, so the result does not depend on scheduling.
+#include <cmath>
+
 #include "cs_internal.h"
 
 namespace cs {
@@ -60,8 +62,8 @@ __global__ void k_momentum(float2* z, float2* x, const float2* xn, float beta, l
   }
 }
 
-// block partial sums of up to three FP64 quantities
-// mode 0: conj(a) b (re, im);  mode 1: |a - b|^2, |b|^2
+// block partial sums of two FP64 quantities
+// mode 0: conj(a) b (re, im);  mode 1: |a - b|^2, |b|^2;  mode 2: |a|, 0
 __global__ __launch_bounds__(kRedThreads) void k_reduce_part(const float2* a,
                                                              const float2* b, long long n,
                                                              int mode, double* part) {
@@ -75,6 +77,8 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_part(const float2* a,
     if (mode == 0) {
       q0 += (double)u.x * v.x + (double)u.y * v.y;
       q1 += (double)u.x * v.y - (double)u.y * v.x;
+    } else if (mode == 2) {
+      q0 += std::sqrt((double)u.x * u.x + (double)u.y * u.y);
     } else {
       const double dx = (double)u.x - v.x, dy = (double)u.y - v.y;
       q0 += dx * dx + dy * dy;
@@ -97,15 +101,29 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_part(const float2* a,
   }
 }
 
-__global__ void k_reduce_final(const double* part, int nparts, double* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double a = 0.0, b = 0.0;
-    for (int i = 0; i < nparts; ++i) {
-      a += part[2 * i];
-      b += part[2 * i + 1];
+// one block: thread t sums partials t, t + 256, ... in order, then a fixed
+// tree over the threads
+__global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double* part, int nparts,
+                                                              double* out) {
+  __shared__ double s0[kRedThreads], s1[kRedThreads];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kRedThreads) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  s0[threadIdx.x] = a;
+  s1[threadIdx.x] = b;
+  __syncthreads();
+  for (int h = kRedThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      s0[threadIdx.x] += s0[threadIdx.x + h];
+      s1[threadIdx.x] += s1[threadIdx.x + h];
     }
-    out[0] = a;
-    out[1] = b;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = s0[0];
+    out[1] = s1[0];
   }
 }
 
@@ -120,8 +138,8 @@ int reduce2(cs_ctx* c, const float2* a, const float2* b, long long n, int mode,
             double out[2]) {
   CS_KLAUNCH(c, K_REDUCE, k_reduce_part, dim3(kRedBlocks), dim3(kRedThreads), 0, c->stream, a, b,
                      n, mode, c->red);
-  CS_KLAUNCH(c, K_REDUCE, k_reduce_final, dim3(1), dim3(64), 0, c->stream, c->red, kRedBlocks,
-                     c->red_out);
+  CS_KLAUNCH(c, K_REDUCE, k_reduce_final, dim3(1), dim3(kRedThreads), 0, c->stream, c->red,
+             kRedBlocks, c->red_out);
   CS_HIP(c, hipGetLastError());
   CS_HIP(c, hipMemcpyAsync(c->host_red, c->red_out, 2 * sizeof(double),
                            hipMemcpyDeviceToHost, c->stream));
@@ -178,6 +196,13 @@ int vec_dist(cs_ctx* c, const float2* a, const float2* b, long long n, double* n
   CS_TRY(reduce2(c, a, b, n, 1, o));
   *num = o[0];
   *den = o[1];
+  return CS_OK;
+}
+
+int vec_abs_sum(cs_ctx* c, const float2* a, long long n, double* out) {
+  double o[2];
+  CS_TRY(reduce2(c, a, a, n, 2, o));
+  *out = o[0];
   return CS_OK;
 }
 

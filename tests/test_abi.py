@@ -14,7 +14,8 @@ LIB = os.path.join(ROOT, "paper_2305_06482_amd", "libcoilsketch.so")
 def declared():
     txt = open(HDR).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    names = re.findall(r"^\s*(?:int|void|const char\s*\*)\s+(\w+)\s*\(", txt, flags=re.M)
+    names = re.findall(r"^\s*(?:int|void|long long|const char\s*\*)\s+(\w+)\s*\(", txt,
+                       flags=re.M)
     return sorted(set(names))
 
 
