@@ -84,7 +84,8 @@ def first_below(dist, thr):
     return None
 
 
-def time_to_accuracy(ctx, y, p, args, log, ref_iters, full_iters, outer_iters, chunk):
+def time_to_accuracy(ctx, y, p, args, log, ref_iters, full_iters, outer_iters, chunk,
+                     cnn=None):
     """Time to d(x^t) = ||x^t - x_inf|| / ||x_inf|| <= thr (Sec. 3.3.1) for the
     plain full-coil FISTA and for Algorithm 1, both in FP32 on this GPU, at
     the paper's 5% criterion and at 1e-2 and 1e-3.
@@ -149,15 +150,22 @@ def time_to_accuracy(ctx, y, p, args, log, ref_iters, full_iters, outer_iters, c
     ev[1].record()
     torch.cuda.synchronize()
     pca_ms = ev[0].elapsed_time(ev[1])
-    res = {"x_inf": ref, "full_coil": full, "sketched_learned": None}
+    res = {"x_inf": ref, "full_coil": full}
     # inner iterations K per subproblem are not fixed by the paper: report
-    # several (outer_iters maps K to the outer-iteration budget)
-    for K, T in outer_iters.items():
+    # several.  runs: (label, K, outer iterations, mode)
+    for label, K, T, mode in outer_iters:
+        if mode == "learned" and cnn is None:
+            continue
         x = torch.zeros(p.shape, dtype=torch.complex64, device=dev)
-        rs = ctx.recon_run(y, mode="sketch", lam=p.lam, T=T, K=K, V=V, S=S, seed=p.seed,
-                           t0=1, step=0.0, n_pow=30, reuse_b=False, x=x, x_ref=x_inf)
-        sk = summarize(rs, 1, K, 0, 31, extra_ms=pca_ms)
-        log(f"{p.name} sketched (Alg. 1, K={K}): final d {sk['final_dist']:.3e}, "
+        rs = ctx.recon_run(y, mode=mode, lam=p.lam, T=T, K=K, V=V, S=S, seed=p.seed,
+                           t0=1, step=0.0, n_pow=30, reuse_b=False, x=x, x_ref=x_inf, cnn=cnn)
+        # the learned mode's decision applies one extra sketched operator
+        sk = summarize(rs, 1, K + (1 if mode == "learned" else 0), 0, 31, extra_ms=pca_ms)
+        if mode == "learned":
+            sk["warm_accepted"] = rs.n_warm_accepted
+            sk["warm_rejected"] = rs.n_warm_rejected
+            sk["ms_warm_decisions"] = rs.ms_warm
+        log(f"{p.name} {label} (K={K}): final d {sk['final_dist']:.3e}, "
             + ", ".join(f"{k}: {v and round(v['total_ms'], 1)} ms" for k, v in sk.items()
                         if k in {f'{t:g}' for t in TTA_THRESHOLDS}))
         sk["speedup_total"] = {}
@@ -165,8 +173,43 @@ def time_to_accuracy(ctx, y, p, args, log, ref_iters, full_iters, outer_iters, c
             k = f"{thr:g}"
             if full.get(k) and sk.get(k):
                 sk["speedup_total"][k] = full[k]["total_ms"] / sk[k]["total_ms"]
-        res[f"sketched_K{K}"] = sk
+        res[f"{label}_K{K}"] = sk
     return res
+
+
+def train_warm_start(args, log, n_problems=6, T=8, K=5, steps=600):
+    """The warm-start network, trained on solver pairs from small cones
+    problems (32^3, 16 coils, sketch 4+4) with the library's MFMA kernels."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2305_06482_amd import CNN, Context, learned
+    t0 = time.time()
+    probs = []
+    for i in range(n_problems):
+        p = synth.make_cones(shape=(32, 32, 32), n_readouts=600, n_samples=96, n_coils=16,
+                             V=4, S=4, seed_base=7000 + 10 * i, lam=5e-4)
+        ctx = Context(p.shape, p.n_coils, "noncart", nsamp=p.coords.shape[0], wav_levels=3)
+        maps = torch.from_numpy(p.maps).to(torch.complex64).cuda()
+        dcf = torch.from_numpy(p.dcf).to(torch.float32).cuda()
+        ctx.set_operator(maps, coords=torch.from_numpy(p.coords).to(torch.float32).cuda(),
+                         dcf=dcf)
+        y = ctx.sense_apply(maps, torch.from_numpy(p.x_true).to(torch.complex64).cuda())
+        y += torch.from_numpy(p.noise).to(torch.complex64).cuda() * \
+            dcf.sqrt()[:, None].to(torch.complex64)
+        probs.append((ctx, y, p.V, p.S, p.seed, p.lam))
+    ins, tgts = learned.collect_pairs(probs, T, K)
+    net = CNN(seed=1)
+    t1 = time.time()
+    losses = learned.train(net, ins, tgts, steps, patch=(32, 32, 32), lr=1e-3)
+    torch.cuda.synchronize()
+    for c, *_ in probs:
+        c.close()
+    info = {"problems": n_problems, "pairs": len(ins), "steps": steps,
+            "loss_first": float(np.mean(losses[:20])), "loss_last": float(np.mean(losses[-20:])),
+            "train_s": round(time.time() - t1, 2), "total_s": round(time.time() - t0, 1)}
+    log(f"warm-start network trained: {info}")
+    return net, info
 
 
 def cartesian_tta(p, args, log):
@@ -184,7 +227,8 @@ def cartesian_tta(p, args, log):
     y = ctx.sense_apply(maps, dt(p.x_true, torch.complex64))
     y += dt(p.noise.reshape(p.shape + (C,)), torch.complex64) * mask[..., None]
     res = time_to_accuracy(ctx, y, p, args, log, ref_iters=20000, full_iters=4000,
-                           outer_iters={5: 800, 20: 250}, chunk=1000)
+                           outer_iters=[("sketched", 5, 800, "sketch"),
+                                        ("sketched", 20, 250, "sketch")], chunk=1000)
     ctx.close()
     return res
 
@@ -443,10 +487,15 @@ def main():
     if not args.no_tta:
         log("time-to-accuracy runs")
         tta = {"thresholds": list(TTA_THRESHOLDS)}
+        net, tinfo = train_warm_start(args, log)
+        tta["warm_start_training"] = tinfo
         tta[p.name] = time_to_accuracy(ctx, y, p, args, log, args.tta_ref_iters,
                                        args.tta_full_iters,
-                                       {args.K: args.tta_outer_iters, 20: 60},
-                                       args.tta_chunk)
+                                       [("sketched", args.K, args.tta_outer_iters, "sketch"),
+                                        ("sketched", 20, 60, "sketch"),
+                                        ("sketched_learned", 20, 60, "learned")],
+                                       args.tta_chunk, cnn=net)
+        net.close()
         if not args.small:
             for pc in (synth.make_cart_small(), synth.make_cart_clinical()):
                 tta[pc.name] = cartesian_tta(pc, args, log)
