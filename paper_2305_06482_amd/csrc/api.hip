@@ -598,6 +598,10 @@ void cs_destroy(cs_ctx* c) {
   fr(c->cov_part); fr(c->cov); fr(c->eig_dev); fr(c->vmaps); fr(c->smaps);
   fr(c->wav1); fr(c->wav2); fr(c->mask); fr(c->rec); fr(c->dcf_orig);
   fr(c->mixB); fr(c->ones);
+  for (int k = 0; k < cs_ctx::kStage; ++k) {
+    if (c->stage[k]) (void)hipHostFree(c->stage[k]);
+    if (c->stage_ev[k]) (void)hipEventDestroy(c->stage_ev[k]);
+  }
   fr(c->items); fr(c->item_off); fr(c->partial);
   for (int a = 0; a < 3; ++a) fr(c->da[a]);
   fr(c->dp_z); fr(c->dp_y); fr(c->da_y1d);

@@ -134,6 +134,13 @@ struct cs_ctx {
   double* eig_dev = nullptr;      // U and lambda from the eigensolver
   void* mixB = nullptr;           // packed bf16 B fragments for coil mixing
   size_t mixB_bytes = 0;
+  // pinned staging ring for the fragments' host-to-device copies; the event
+  // of a slot marks its last copy, so a slot is rewritten only after it
+  static constexpr int kStage = 4;
+  void* stage[kStage] = {};
+  size_t stage_bytes[kStage] = {};
+  hipEvent_t stage_ev[kStage] = {};
+  int stage_next = 0;
 
   // wavelet work
   float2* wav1 = nullptr;

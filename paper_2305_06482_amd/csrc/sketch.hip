@@ -401,9 +401,22 @@ int coil_mix(cs_ctx* c, const float2* in, int in_ldc, int in_c0, int cin, const 
     CS_HIP(c, hipMalloc(&c->mixB, bytes));
     c->mixB_bytes = bytes;
   }
-  CS_HIP(c, hipMemcpyAsync(c->mixB, frag.data(), bytes, hipMemcpyHostToDevice, c->stream));
-  // the host buffer must outlive the copy
-  CS_HIP(c, hipStreamSynchronize(c->stream));
+  // stage through a pinned ring slot whose previous copy has completed (no
+  // stream-wide synchronisation)
+  const int k = c->stage_next;
+  c->stage_next = (k + 1) % cs_ctx::kStage;
+  if (c->stage_ev[k]) CS_HIP(c, hipEventSynchronize(c->stage_ev[k]));
+  else CS_HIP(c, hipEventCreateWithFlags(&c->stage_ev[k], hipEventDisableTiming));
+  if (bytes > c->stage_bytes[k]) {
+    if (c->stage[k]) CS_HIP(c, hipHostFree(c->stage[k]));
+    c->stage[k] = nullptr;
+    c->stage_bytes[k] = 0;
+    CS_HIP(c, hipHostMalloc(&c->stage[k], bytes, 0));
+    c->stage_bytes[k] = bytes;
+  }
+  std::memcpy(c->stage[k], frag.data(), bytes);
+  CS_HIP(c, hipMemcpyAsync(c->mixB, c->stage[k], bytes, hipMemcpyHostToDevice, c->stream));
+  CS_HIP(c, hipEventRecord(c->stage_ev[k], c->stream));
   const long long tiles = (c->D + 15) / 16;
   const unsigned nb = (unsigned)((tiles + 3) / 4);
   CS_KLAUNCH(c, K_MIX, k_coil_mix, dim3(nb), dim3(256), 0, c->stream, in, in_ldc, in_c0, cin,
