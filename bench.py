@@ -30,6 +30,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per spreading launch (spread kernel + merge of its partial tiles)
+# over the timed mix of 12- and 16-coil launches on the full cones workload,
+# from FETCH_SIZE (x 2.00) and WRITE_SIZE (x 1.00) counter runs calibrated on
+# the plain copy kernel; to be re-measured (or set to None) when those kernels
+# change.
+SPREAD_TRAFFIC_BYTES = 10.94e9
 METRIC = ("normal_apply GB/s & %roofline; time-to-1e-3 NRMSE sketched+learned vs "
           "full-coil")
 
@@ -448,7 +454,9 @@ def main():
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                 "avg_launch_ms": kern[dom]["ms"] / kern[dom]["launches"],
-                "bytes_per_launch": kern[dom]["bytes_per_launch"], "traffic": None}
+                "bytes_per_launch": kern[dom]["bytes_per_launch"],
+                "traffic": (SPREAD_TRAFFIC_BYTES if dom == "spread" and not args.small
+                            else None)}
 
     out = {
         "metric": METRIC,
