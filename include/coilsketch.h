@@ -245,7 +245,7 @@ int cs_batch_recon(cs_batch* b, const void* const* y, const cs_recon_params* p,
                    void* const* x, int use_graph, cs_batch_stats* st);
 
 /* ---- spreading work-group shapes and their autotuner --------------------- */
-#define CS_SPREAD_NCFG 6
+#define CS_SPREAD_NCFG 7
 /* Select spreading shape cfg in [0, CS_SPREAD_NCFG) for this context (all
  * shapes give bit-identical results; they differ only in speed). */
 int cs_set_spread_cfg(cs_ctx* ctx, int cfg);

@@ -37,7 +37,7 @@ EXPORTED = [
     "cs_cnn_get_params", "cs_cnn_set_params", "cs_cnn_forward", "cs_cnn_loss_grad",
     "cs_cnn_train_step", "cs_cnn_collect",
 ]
-SPREAD_NCFG = 6
+SPREAD_NCFG = 7
 NKERNELS = 12
 KERNEL_KINDS = ["fft_pass", "interp", "spread", "gather", "wavelet", "soft", "vec", "reduce",
                 "covariance", "eigensolver", "coil_mix", "spread_merge"]

@@ -202,6 +202,8 @@ __global__ __launch_bounds__(64 * NW) void k_spread(
   const int tap = lane % H::NTAPS, cslot = lane / H::NTAPS;
   const int dx = tap & 3, dy = (tap >> 2) & 3, dz = tap >> 4;
   const int q0 = (wave * H::LPC + cslot) * CW;  // first group coil of this lane
+  // waves whose coils all lie beyond the chunk only help with the staging
+  const bool active = (wave * H::LPC) * CW < cga;
   float2 racc[CW];
 #pragma unroll
   for (int q = 0; q < CW; ++q) racc[q] = make_float2(0.f, 0.f);
@@ -263,7 +265,7 @@ __global__ __launch_bounds__(64 * NW) void k_spread(
     }
     __syncthreads();
     if (k0 + SB < kend) prefetch(k0 + SB, min(SB, kend - k0 - SB));
-    const int nr = s_nr;
+    const int nr = active ? s_nr : -1;
     int s = 0;
     for (int r = -1; r < nr; ++r) {
       const int s1 = (r + 1 < nr) ? s_rs[r + 1] : n;
@@ -474,6 +476,7 @@ int spread_launch(cs_ctx* c, const float2* vals, int cb, float2* grid) {
   if ((size_t)c->n_items * ng * H::EXT * CG > c->partial_elems)
     return fail(c, CS_EINVAL, "spread partial buffer too small");
   const size_t lds = spread_lds_bytes<NDIM, NW, CW>();
+  if (lds > 160 * 1024) return fail(c, CS_EINVAL, "spread tile does not fit in LDS");
   if (c->n_items > 0) {
     auto kern = k_spread<NDIM, NW, CW>;
     if (lds > 64 * 1024)
@@ -503,6 +506,18 @@ int spread_dispatch(cs_ctx* c, const float2* vals, int cb, float2* grid) {
     case 3: return spread_launch<NDIM, 1, 4>(c, vals, cb, grid);
     case 4: return spread_launch<NDIM, 4, 2>(c, vals, cb, grid);
     case 5: return spread_launch<NDIM, 1, 3>(c, vals, cb, grid);
+    case 6:
+      // all coils of the chunk in one work-group where the LDS allows (one
+      // wave per coil), so every sample is staged once
+      if constexpr (NDIM == 3) {
+        if (cb <= 4) return spread_launch<NDIM, 4, 1>(c, vals, cb, grid);
+        if (cb <= 6) return spread_launch<NDIM, 6, 1>(c, vals, cb, grid);
+        if (cb <= 8) return spread_launch<NDIM, 8, 1>(c, vals, cb, grid);
+        if (cb <= 12) return spread_launch<NDIM, 12, 1>(c, vals, cb, grid);
+        return spread_launch<NDIM, 8, 1>(c, vals, cb, grid);
+      } else {
+        return spread_launch<NDIM, 4, 1>(c, vals, cb, grid);
+      }
     default: return spread_launch<NDIM, 4, 1>(c, vals, cb, grid);
   }
 }
