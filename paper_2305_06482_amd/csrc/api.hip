@@ -305,10 +305,15 @@ int nc_adjoint(cs_ctx* c, const float2* maps, int ldc, int c0, int cb, const flo
   return nc_adjoint_grid(c, c->gridA, c->gridB, maps, ldc, c0, cb, out);
 }
 
-int check_ready(cs_ctx* c, const void* maps, int ncoil, const void* a, const void* b) {
+// data_arg: which of a (1) or b (2) is sample data, which may be NULL for an
+// empty trajectory (0: both are images)
+int check_ready(cs_ctx* c, const void* maps, int ncoil, const void* a, const void* b,
+                int data_arg = 0) {
   if (!c) return CS_EINVAL;
   if (!c->have_op) return fail(c, CS_EINVAL, "cs_set_operator has not been called");
-  if (!maps || !a || !b) return fail(c, CS_EINVAL, "null pointer");
+  const bool empty = c->g.kind == CS_NONCART && c->N == 0;
+  if (!maps || (!a && !(empty && data_arg == 1)) || (!b && !(empty && data_arg == 2)))
+    return fail(c, CS_EINVAL, "null pointer");
   if (ncoil < 1 || ncoil > 64) return fail(c, CS_EINVAL, "ncoil must be in [1, 64]");
   return CS_OK;
 }
@@ -644,7 +649,7 @@ int cs_set_operator(cs_ctx* c, const void* maps, const uint8_t* mask, const floa
     CS_HIP(c, hipMemcpy(c->mask, h.data(), c->D, hipMemcpyHostToDevice));
     c->mask1d = oned;
   } else {
-    if (!coords) return fail(c, CS_EINVAL, "non-Cartesian operator needs coordinates");
+    if (!coords && c->N > 0) return fail(c, CS_EINVAL, "non-Cartesian operator needs coordinates");
     if (c->rec) {
       CS_HIP(c, hipFree(c->rec)); c->rec = nullptr;
       CS_HIP(c, hipFree(c->items)); c->items = nullptr;
@@ -664,12 +669,12 @@ int cs_set_operator(cs_ctx* c, const void* maps, const uint8_t* mask, const floa
 }
 
 int sense_apply(cs_ctx* c, const void* maps, int ncoil, const void* x, void* y) {
-  CS_TRY(check_ready(c, maps, ncoil, x, y));
+  CS_TRY(check_ready(c, maps, ncoil, x, y, 2));
   return chunk_loop(c, ncoil, op_apply, (const float2*)maps, (const float2*)x, (float2*)y);
 }
 
 int sense_adjoint(cs_ctx* c, const void* maps, int ncoil, const void* y, void* x) {
-  CS_TRY(check_ready(c, maps, ncoil, y, x));
+  CS_TRY(check_ready(c, maps, ncoil, y, x, 1));
   return chunk_loop(c, ncoil, op_adjoint, (const float2*)maps, (const float2*)y, (float2*)x);
 }
 

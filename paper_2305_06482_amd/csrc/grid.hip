@@ -554,8 +554,10 @@ int setup_noncart(cs_ctx* c, const float* coords_dev, const float* dcf_dev) {
   const int nd = c->ndim;
   if (N > 0x7fffffffLL) return fail(c, CS_EINVAL, "more than 2^31 - 1 samples");
   std::vector<float> coords((size_t)N * nd), dcf;
-  CS_HIP(c, hipMemcpy(coords.data(), coords_dev, sizeof(float) * N * nd,
-                      hipMemcpyDeviceToHost));
+  if (N > 0)
+    CS_HIP(c, hipMemcpy(coords.data(), coords_dev, sizeof(float) * N * nd,
+                        hipMemcpyDeviceToHost));
+  if (N == 0) dcf_dev = nullptr;  // empty trajectory: the zero operator
   if (dcf_dev) {
     dcf.resize(N);
     CS_HIP(c, hipMemcpy(dcf.data(), dcf_dev, sizeof(float) * N, hipMemcpyDeviceToHost));
@@ -624,7 +626,8 @@ int setup_noncart(cs_ctx* c, const float* coords_dev, const float* dcf_dev) {
   for (long long t = 0; t < c->ntiles; ++t) toff[t + 1] += toff[t];
 
   CS_HIP(c, hipMalloc(&c->rec, sizeof(SampleRec) * std::max(1LL, N)));
-  CS_HIP(c, hipMemcpy(c->rec, srec.data(), sizeof(SampleRec) * N, hipMemcpyHostToDevice));
+  if (N > 0)
+    CS_HIP(c, hipMemcpy(c->rec, srec.data(), sizeof(SampleRec) * N, hipMemcpyHostToDevice));
   if (dcf_dev) {
     CS_HIP(c, hipMalloc(&c->dcf_orig, sizeof(float) * N));
     CS_HIP(c, hipMemcpy(c->dcf_orig, dcf.data(), sizeof(float) * N, hipMemcpyHostToDevice));
