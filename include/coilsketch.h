@@ -257,6 +257,15 @@ int cs_set_spread_cfg(cs_ctx* ctx, int cfg);
 int cs_autotune_spread(cs_ctx* ctx, const void* maps, int ncoil, int reps, int* best,
                        double* ms);
 
+/* Interpolation variant for non-Cartesian contexts (cfg in [0,
+ * CS_INTERP_NCFG)): 0 gathers every tap of a sample from the grid in global
+ * memory; 1 (the default), 2 and 3 copy each work item's halo'd grid tile
+ * into LDS first and gather from there, for coil groups of at most 8 (1), 12
+ * (2) or 4 (3) coils in 3D.  All sum the taps in the same order.  The
+ * environment variable CS_INTERP_CFG sets the default of new operators. */
+#define CS_INTERP_NCFG 4
+int cs_set_interp_cfg(cs_ctx* ctx, int cfg);
+
 /* ---- building blocks exposed for testing and benchmarking ---------------- */
 
 /* Periodized db4 wavelet prox  out = Psi^H soft(Psi v, tau)  (Sec. 2.1,

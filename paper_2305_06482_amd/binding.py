@@ -33,11 +33,13 @@ EXPORTED = [
     "cs_dwt", "cs_idwt", "cs_coil_mix", "cs_dot", "cs_power_iteration", "cs_grid_shape",
     "cs_profile_enable", "cs_profile_read", "cs_batch_create", "cs_batch_destroy",
     "cs_batch_last_error", "cs_batch_recon", "cs_set_spread_cfg", "cs_autotune_spread",
+    "cs_set_interp_cfg",
     "cs_cnn_create", "cs_cnn_destroy", "cs_cnn_last_error", "cs_cnn_num_params",
     "cs_cnn_get_params", "cs_cnn_set_params", "cs_cnn_forward", "cs_cnn_loss_grad",
     "cs_cnn_train_step", "cs_cnn_collect",
 ]
 SPREAD_NCFG = 7
+INTERP_NCFG = 4
 NKERNELS = 12
 KERNEL_KINDS = ["fft_pass", "interp", "spread", "gather", "wavelet", "soft", "vec", "reduce",
                 "covariance", "eigensolver", "coil_mix", "spread_merge"]
@@ -151,6 +153,7 @@ def load() -> ctypes.CDLL:
     lib.cs_batch_recon.argtypes = [vp, vp, ctypes.POINTER(ReconParams), vp, ci,
                                    ctypes.POINTER(BatchStats)]
     lib.cs_set_spread_cfg.argtypes = [vp, ci]
+    lib.cs_set_interp_cfg.argtypes = [vp, ci]
     lib.cs_autotune_spread.argtypes = [vp, vp, ci, ci, ctypes.POINTER(ci), vp]
     lib.cs_cnn_create.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(vp)]
     lib.cs_cnn_destroy.argtypes = [vp]
@@ -485,6 +488,12 @@ class Context:
     def set_spread_cfg(self, cfg):
         """Select a spreading work-group shape (0 .. SPREAD_NCFG - 1)."""
         self._check(self.lib.cs_set_spread_cfg(self._ctx, int(cfg)), "cs_set_spread_cfg")
+
+    def set_interp_cfg(self, cfg):
+        """Select the interpolation variant: 0 global-memory gather, 1 LDS
+        tiles of at most 8 coils (the default), 2 and 3 LDS tiles of at most 12
+        and 4 coils."""
+        self._check(self.lib.cs_set_interp_cfg(self._ctx, int(cfg)), "cs_set_interp_cfg")
 
     def autotune_spread(self, maps, reps=3):
         """Time every spreading shape on a normal apply with `maps` and keep

@@ -245,6 +245,13 @@ int cs_set_spread_cfg(cs_ctx* c, int cfg) {
   return CS_OK;
 }
 
+int cs_set_interp_cfg(cs_ctx* c, int cfg) {
+  if (!c) return CS_EINVAL;
+  if (cfg < 0 || cfg >= CS_INTERP_NCFG) return fail(c, CS_EINVAL, "interpolation variant");
+  c->interp_cfg = cfg;
+  return CS_OK;
+}
+
 int cs_autotune_spread(cs_ctx* c, const void* maps, int ncoil, int reps, int* best,
                        double* ms) {
   if (!c || !maps || !best || ncoil < 1 || ncoil > c->C || reps < 1) return CS_EINVAL;

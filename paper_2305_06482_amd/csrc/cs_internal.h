@@ -114,6 +114,7 @@ struct cs_ctx {
   float2* partial = nullptr;      // halo'd partial tile of every slot
   size_t partial_elems = 0;       // float2 capacity of `partial`
   int spread_cfg = 0;             // spread work-group shape (see launch_spread)
+  int interp_cfg = 1;             // interpolation: 0 per-sample gather, 1/2 LDS tiles
 
   // work buffers
   float2* gridA = nullptr;        // M * kCoilChunk

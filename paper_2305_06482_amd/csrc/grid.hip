@@ -134,6 +134,7 @@ __global__ __launch_bounds__(256) void k_interp(const float2* __restrict__ G, in
     if (c < cb) dst[c] = make_float2(acc[c].x * s, acc[c].y * s);
 }
 
+
 __device__ __forceinline__ float sel4(const float* w, int i) {
   return i == 0 ? w[0] : (i == 1 ? w[1] : (i == 2 ? w[2] : w[3]));
 }
@@ -157,6 +158,133 @@ struct Halo {
   static constexpr int NTAPS = NDIM == 3 ? 64 : 16;
   static constexpr int LPC = 64 / NTAPS;  // coil slots per wave
 };
+
+// Tiled interpolation: one work-group per spread work item and coil group.
+// The group first copies the item's halo'd tile of the grid (the tile grown
+// by the 3-voxel reach of the kernel, wrapped modulo the grid) into LDS,
+// planar per (coil, re/im) as in the spreading accumulator, and then one
+// thread per sample sums its 4^d taps from LDS in the same order as
+// k_interp (z, y, x taps, weight wz wy wx), so both give the same values.
+// Every tap of a sample lies in the halo'd tile of the tile that holds its
+// first tap, so no other memory is read.
+template <int NDIM, int CG, int NT>
+__global__ __launch_bounds__(NT) void k_interp_tile(
+    const float2* __restrict__ G, int mx, int my, int mz, int cb,
+    const SampleRec* __restrict__ rec, const int4* __restrict__ items, int ntx, int nty,
+    int wmode, float2* __restrict__ out, int ldc, int c0, int caller_order) {
+  using H = Halo<NDIM>;
+  extern __shared__ float lds[];  // [CG][2][PLANE]
+  const int4 it = items[blockIdx.x];
+  const int tile = it.x, kbeg = it.y, kend = it.z;
+  const int cg0 = blockIdx.y * CG, cga = min(CG, cb - cg0);
+  const int ix = tile % ntx, iy = (tile / ntx) % nty, iz = tile / (ntx * nty);
+  const int x0 = ix * H::TX, y0 = iy * H::TY, z0 = iz * H::TZ;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < H::EXT * CG; i += NT) {
+    const int e = i / CG, q = i - e * CG;
+    const int lx = e % H::EX, ly = (e / H::EX) % H::EY, lz = e / (H::EX * H::EY);
+    // wrap into the grid by subtraction (a runtime modulo costs dozens of
+    // instructions per element): the coordinate is below m + EX - 1 and the
+    // grid is at least 4 long per axis, so (EX + 3) / 4 subtractions suffice
+    int gx = x0 + lx, gy = y0 + ly, gz = NDIM == 3 ? z0 + lz : 0;
+#pragma unroll
+    for (int w = 0; w < (H::EX + 3) / 4; ++w) {
+      gx -= gx >= mx ? mx : 0;
+      gy -= gy >= my ? my : 0;
+      if (NDIM == 3) gz -= gz >= mz ? mz : 0;
+    }
+    float2 v = make_float2(0.f, 0.f);
+    if (q < cga) v = G[(((long long)gz * my + gy) * mx + gx) * cb + cg0 + q];
+    const int a = lz * H::PZ + ly * H::PY + lx;
+    lds[(size_t)q * 2 * H::PLANE + a] = v.x;
+    lds[(size_t)q * 2 * H::PLANE + H::PLANE + a] = v.y;
+  }
+  __syncthreads();
+  for (int k = kbeg + tid; k < kend; k += NT) {
+    const SampleRec r = rec[k];
+    const int b0 = (NDIM == 3 ? (r.bz - z0) * H::PZ : 0) + (r.by - y0) * H::PY + (r.bx - x0);
+    float2 acc[CG];
+#pragma unroll
+    for (int q = 0; q < CG; ++q) acc[q] = make_float2(0.f, 0.f);
+    const int nzt = NDIM == 3 ? 4 : 1;
+    // one row of four x taps per step: unrolling further lets the compiler
+    // hoist the LDS reads of many rows and run out of registers.  The row
+    // weights are picked by selects: indexing the record's arrays with a
+    // loop counter would put the record in scratch memory.
+#pragma unroll 1
+    for (int dz = 0; dz < nzt; ++dz) {
+      const float wz = NDIM == 3 ? sel4(r.wz, dz) : 1.f;
+#pragma unroll 1
+      for (int dy = 0; dy < 4; ++dy) {
+        const float wyz = wz * sel4(r.wy, dy);
+        const int row = b0 + dz * H::PZ + dy * H::PY;
+#pragma unroll
+        for (int dx = 0; dx < 4; ++dx) {
+          const float w = wyz * r.wx[dx];
+#pragma unroll
+          for (int q = 0; q < CG; ++q) {
+            const float* pl = lds + (size_t)q * 2 * H::PLANE + row + dx;
+            acc[q].x += w * pl[0];
+            acc[q].y += w * pl[H::PLANE];
+          }
+        }
+      }
+    }
+    const float s = wmode == W_FULL ? r.w : (wmode == W_SQRT ? r.sw : 1.f);
+    const long long o = caller_order ? (long long)r.orig : k;
+    float2* dst = out + o * ldc + c0 + cg0;
+#pragma unroll
+    for (int q = 0; q < CG; ++q)
+      if (q < cga) dst[q] = make_float2(acc[q].x * s, acc[q].y * s);
+  }
+}
+
+template <int NDIM, int CG>
+size_t interp_tile_lds_bytes() {
+  return sizeof(float) * (size_t)CG * 2 * Halo<NDIM>::PLANE;
+}
+
+// 512 threads per group in 3D, where the LDS tile allows only one or two
+// groups per compute unit
+template <int NDIM, int CG>
+int interp_tile_launch(cs_ctx* c, const float2* grid, int cb, int wmode, float2* out,
+                       int ldc, int c0, int caller_order) {
+  const size_t lds = interp_tile_lds_bytes<NDIM, CG>();
+  if (lds > 160 * 1024) return fail(c, CS_EINVAL, "interpolation tile does not fit in LDS");
+  const int ng = (cb + CG - 1) / CG;
+  if (c->n_items == 0) return CS_OK;
+  constexpr int NT = NDIM == 3 ? 512 : 256;
+  auto kern = k_interp_tile<NDIM, CG, NT>;
+  if (lds > 64 * 1024)
+    CS_HIP(c, hipFuncSetAttribute((const void*)kern,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  CS_KLAUNCH(c, K_INTERP, kern, dim3((unsigned)c->n_items, (unsigned)ng), dim3(NT), lds,
+             c->stream, grid, c->mx, c->my, c->mz, cb, c->rec, c->items, c->ntile[2],
+             c->ntile[1], wmode, out, ldc, c0, caller_order);
+  CS_HIP(c, hipGetLastError());
+  return CS_OK;
+}
+
+// coil groups of at most cmax coils (3D: 8 planar coils of the 11^3 tile
+// take 85 KB of LDS, 12 take 128 KB) or 16 (2D); the group size is the chunk
+// split evenly
+template <int NDIM>
+int interp_tile_dispatch(cs_ctx* c, const float2* grid, int cb, int wmode, float2* out,
+                         int ldc, int c0, int caller_order, int cmax) {
+  if (NDIM == 2) cmax = 16;
+  const int ng = (cb + cmax - 1) / cmax;
+  const int cg = (cb + ng - 1) / ng;
+#define CS_ITILE(CG) \
+  return interp_tile_launch<NDIM, CG>(c, grid, cb, wmode, out, ldc, c0, caller_order)
+  if (cg <= 2) CS_ITILE(2);
+  if (cg <= 4) CS_ITILE(4);
+  if (cg <= 6) CS_ITILE(6);
+  if (cg <= 8) CS_ITILE(8);
+  if (cg <= 12) CS_ITILE(12);
+  if constexpr (NDIM == 2) CS_ITILE(16);
+#undef CS_ITILE
+  return fail(c, CS_EINVAL, "interpolation coil group");
+}
 
 constexpr int kSpreadBatch = 64;  // samples staged in LDS per step
 constexpr int kSpreadRecPitch = 13;  // staged record: packed first tap + 12 weights
@@ -450,6 +578,12 @@ int launch_interp(cs_ctx* c, const float2* grid, int cb, int wmode, float2* out,
                   int ldc, int c0, int caller_order) {
   if (cb < 1 || cb > kCoilChunk) return fail(c, CS_EINVAL, "interp coil chunk");
   if (c->N == 0) return CS_OK;
+  if (c->interp_cfg >= 1) {
+    const int cmax = c->interp_cfg == 1 ? 8 : (c->interp_cfg == 2 ? 12 : 4);
+    return c->ndim == 3
+               ? interp_tile_dispatch<3>(c, grid, cb, wmode, out, ldc, c0, caller_order, cmax)
+               : interp_tile_dispatch<2>(c, grid, cb, wmode, out, ldc, c0, caller_order, cmax);
+  }
   return c->ndim == 3 ? interp_dispatch<3>(c, grid, cb, wmode, out, ldc, c0, caller_order)
                       : interp_dispatch<2>(c, grid, cb, wmode, out, ldc, c0, caller_order);
 }
@@ -577,6 +711,8 @@ int setup_noncart(cs_ctx* c, const float* coords_dev, const float* dcf_dev) {
     if (m[a] < 4) return fail(c, CS_EINVAL, "NUFFT grid shorter than the kernel");
   const char* cfg = std::getenv("CS_SPREAD_CFG");
   c->spread_cfg = cfg ? std::atoi(cfg) : 0;
+  const char* icfg = std::getenv("CS_INTERP_CFG");
+  c->interp_cfg = icfg ? std::atoi(icfg) : 1;
   for (int a = 0; a < 3; ++a) c->ntile[a] = (m[a] + c->tile[a] - 1) / c->tile[a];
   c->ntiles = (long long)c->ntile[0] * c->ntile[1] * c->ntile[2];
 
