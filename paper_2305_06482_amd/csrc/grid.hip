@@ -324,7 +324,10 @@ __global__ __launch_bounds__(64 * NW) void k_spread(
   const int cg0 = g * CG, cga = min(CG, cb - cg0);
   const int ix = tile % ntx, iy = (tile / ntx) % nty, iz = tile / (ntx * nty);
   const int x0 = ix * H::TX, y0 = iy * H::TY, z0 = iz * H::TZ;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  // the wave index through readfirstlane: the compiler then knows it (and
+  // all that depends only on it) to be uniform across the wave
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6),
+            lane = tid & 63;
   for (int i = tid; i < CG * 2 * H::PLANE; i += NT) acc[i] = 0.f;
 
   const int tap = lane % H::NTAPS, cslot = lane / H::NTAPS;
@@ -393,10 +396,12 @@ __global__ __launch_bounds__(64 * NW) void k_spread(
     }
     __syncthreads();
     if (k0 + SB < kend) prefetch(k0 + SB, min(SB, kend - k0 - SB));
-    const int nr = active ? s_nr : -1;
+    // the run bounds are the same for every lane: reading them through
+    // readfirstlane keeps the loop control in scalar registers
+    const int nr = active ? __builtin_amdgcn_readfirstlane(s_nr) : -1;
     int s = 0;
     for (int r = -1; r < nr; ++r) {
-      const int s1 = (r + 1 < nr) ? s_rs[r + 1] : n;
+      const int s1 = (r + 1 < nr) ? __builtin_amdgcn_readfirstlane(s_rs[r + 1]) : n;
       if (r >= 0) {
         // close the current run, open the one starting at s
         if (rkey >= 0) {
@@ -410,7 +415,7 @@ __global__ __launch_bounds__(64 * NW) void k_spread(
             racc[q] = make_float2(0.f, 0.f);
           }
         }
-        rkey = __float_as_int(srec[s * SRP]);
+        rkey = __builtin_amdgcn_readfirstlane(__float_as_int(srec[s * SRP]));
         const int lx = (rkey & 0xff) + dx, ly = ((rkey >> 8) & 0xff) + dy,
                   lz = NDIM == 3 ? (rkey >> 16) + dz : 0;
         raddr = lz * H::PZ + ly * H::PY + lx;
