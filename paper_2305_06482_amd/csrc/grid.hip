@@ -180,12 +180,13 @@ __global__ __launch_bounds__(NT) void k_interp_tile(
   const int ix = tile % ntx, iy = (tile / ntx) % nty, iz = tile / (ntx * nty);
   const int x0 = ix * H::TX, y0 = iy * H::TY, z0 = iz * H::TZ;
   const int tid = threadIdx.x;
-  for (int i = tid; i < H::EXT * CG; i += NT) {
-    const int e = i / CG, q = i - e * CG;
+  // one thread per voxel of the halo'd tile copies the group's coils, so the
+  // index arithmetic is paid once per voxel
+  for (int e = tid; e < H::EXT; e += NT) {
     const int lx = e % H::EX, ly = (e / H::EX) % H::EY, lz = e / (H::EX * H::EY);
     // wrap into the grid by subtraction (a runtime modulo costs dozens of
-    // instructions per element): the coordinate is below m + EX - 1 and the
-    // grid is at least 4 long per axis, so (EX + 3) / 4 subtractions suffice
+    // instructions): the coordinate is below m + EX - 1 and the grid is at
+    // least 4 long per axis, so (EX + 3) / 4 subtractions suffice
     int gx = x0 + lx, gy = y0 + ly, gz = NDIM == 3 ? z0 + lz : 0;
 #pragma unroll
     for (int w = 0; w < (H::EX + 3) / 4; ++w) {
@@ -193,11 +194,15 @@ __global__ __launch_bounds__(NT) void k_interp_tile(
       gy -= gy >= my ? my : 0;
       if (NDIM == 3) gz -= gz >= mz ? mz : 0;
     }
-    float2 v = make_float2(0.f, 0.f);
-    if (q < cga) v = G[(((long long)gz * my + gy) * mx + gx) * cb + cg0 + q];
+    const float2* src = G + (((long long)gz * my + gy) * mx + gx) * cb + cg0;
     const int a = lz * H::PZ + ly * H::PY + lx;
-    lds[(size_t)q * 2 * H::PLANE + a] = v.x;
-    lds[(size_t)q * 2 * H::PLANE + H::PLANE + a] = v.y;
+#pragma unroll
+    for (int q = 0; q < CG; ++q) {
+      float2 v = make_float2(0.f, 0.f);
+      if (q < cga) v = src[q];
+      lds[(size_t)q * 2 * H::PLANE + a] = v.x;
+      lds[(size_t)q * 2 * H::PLANE + H::PLANE + a] = v.y;
+    }
   }
   __syncthreads();
   for (int k = kbeg + tid; k < kend; k += NT) {
@@ -444,13 +449,16 @@ __global__ __launch_bounds__(64 * NW) void k_spread(
     }
   }
   __syncthreads();
-  // write-out: slot layout [slot][group][EXT][CG]
+  // write-out: slot layout [slot][group][EXT][CG]; one thread per voxel
+  // writes the group's CG coils of that voxel (contiguous)
   float2* dst = P + ((size_t)slot * ng + g) * H::EXT * CG;
-  for (int i = tid; i < H::EXT * CG; i += NT) {
-    const int e = i / CG, q = i - e * CG;
+  for (int e = tid; e < H::EXT; e += NT) {
     const int lx = e % H::EX, ly = (e / H::EX) % H::EY, lz = e / (H::EX * H::EY);
     const int a = lz * H::PZ + ly * H::PY + lx;
-    dst[i] = make_float2(acc[(size_t)q * 2 * H::PLANE + a],
+    float2* d = dst + (size_t)e * CG;
+#pragma unroll
+    for (int q = 0; q < CG; ++q)
+      d[q] = make_float2(acc[(size_t)q * 2 * H::PLANE + a],
                          acc[(size_t)q * 2 * H::PLANE + H::PLANE + a]);
   }
 }
