@@ -292,7 +292,10 @@ int interp_tile_dispatch(cs_ctx* c, const float2* grid, int cb, int wmode, float
 }
 
 constexpr int kSpreadBatch = 64;  // samples staged in LDS per step
-constexpr int kSpreadRecPitch = 13;  // staged record: packed first tap + 12 weights
+// staged record: packed first tap, wx[4], then wy[dy] * wz[dz] at 4 dz + dy
+// (the products are formed once per sample in the staging, not by every
+// coil wave for every tap)
+constexpr int kSpreadRecPitch = 21;
 
 // One work-group = one work item (a contiguous range of the samples of one
 // tile, in sorted order) and one group of CG = NW * LPC * CW coils.  Lane l
@@ -383,7 +386,10 @@ __global__ __launch_bounds__(64 * NW) void k_spread(
       float* d = srec + tid * SRP;
       d[0] = __int_as_float(pkey);
 #pragma unroll
-      for (int q = 0; q < 12; ++q) d[1 + q] = pw[q];
+      for (int q = 0; q < 4; ++q) d[1 + q] = pw[q];
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        d[5 + q] = NDIM == 3 ? pw[4 + (q & 3)] * pw[8 + (q >> 2)] : pw[4 + (q & 3)];
     }
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
@@ -426,11 +432,10 @@ __global__ __launch_bounds__(64 * NW) void k_spread(
         raddr = lz * H::PZ + ly * H::PY + lx;
       }
       // samples of the run: register accumulation, no branches
-#pragma unroll 2
+#pragma unroll 4
       for (; s < s1; ++s) {
         const float* d = srec + s * SRP;
-        float w = d[1 + dx] * d[5 + dy];
-        if (NDIM == 3) w *= d[9 + dz];
+        const float w = d[1 + dx] * d[5 + dy + 4 * dz];
         const int vb = 2 * (s * CG + q0);
 #pragma unroll
         for (int q = 0; q < CW; ++q) {
