@@ -250,9 +250,10 @@ __device__ __forceinline__ void dftR(float2* v, int dir) {
   else dft5(v, dir);
 }
 
-template <int L, int TC, int R, int NS>
-__device__ __forceinline__ void fft_stage(float2* buf, const float2* tw, int tr, int tc,
-                                          int dir) {
+// DIR (-1 forward, +1 inverse) is a template parameter so that the
+// multiplications by +-i and the twiddle conjugation fold at compile time
+template <int L, int TC, int R, int NS, int DIR>
+__device__ __forceinline__ void fft_stage(float2* buf, const float2* tw, int tr, int tc) {
   constexpr int TR = 256 / TC;
   constexpr int NBF = L / R;
   constexpr int NB = (NBF + TR - 1) / TR;
@@ -272,13 +273,16 @@ __device__ __forceinline__ void fft_stage(float2* buf, const float2* tw, int tr,
     const int j = tr + b * TR;
     if (NB * TR == NBF || j < NBF) {
       const int k = j % NS;
+      // the first stage's twiddles are all e^0 = 1 (exactly): skipped
+      if constexpr (NS > 1) {
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        float2 w = tw[k * r * TSTEP];
-        if (dir > 0) w.y = -w.y;
-        v[b][r] = cmul(v[b][r], w);
+        for (int r = 1; r < R; ++r) {
+          float2 w = tw[k * r * TSTEP];
+          if (DIR > 0) w.y = -w.y;
+          v[b][r] = cmul(v[b][r], w);
+        }
       }
-      dftR<R>(v[b], dir);
+      dftR<R>(v[b], DIR);
       const int base = (j / NS) * NS * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) buf[(base + r * NS) * TC + tc] = v[b][r];
@@ -287,15 +291,23 @@ __device__ __forceinline__ void fft_stage(float2* buf, const float2* tw, int tr,
   __syncthreads();
 }
 
-template <int L, int TC, int S, int NS>
-__device__ __forceinline__ void fft_stages(float2* buf, const float2* tw, int tr, int tc,
-                                           int dir) {
+template <int L, int TC, int S, int NS, int DIR>
+__device__ __forceinline__ void fft_stages(float2* buf, const float2* tw, int tr, int tc) {
   constexpr RadPlan P = make_radplan(L);
   if constexpr (S < P.n) {
     constexpr int R = P.r[S];
-    fft_stage<L, TC, R, NS>(buf, tw, tr, tc, dir);
-    fft_stages<L, TC, S + 1, NS * R>(buf, tw, tr, tc, dir);
+    fft_stage<L, TC, R, NS, DIR>(buf, tw, tr, tc);
+    fft_stages<L, TC, S + 1, NS * R, DIR>(buf, tw, tr, tc);
   }
+}
+
+template <int L, int TC>
+__device__ __forceinline__ void fft_panel(float2* buf, const float2* tw, int tr, int tc,
+                                          int dir) {
+  if (dir < 0)
+    fft_stages<L, TC, 0, 1, -1>(buf, tw, tr, tc);
+  else
+    fft_stages<L, TC, 0, 1, 1>(buf, tw, tr, tc);
 }
 
 template <int L, int TC>
@@ -344,14 +356,14 @@ __global__ __launch_bounds__(256) void k_pass_t(PassArgs a) {
   }
   __syncthreads();
 
-  fft_stages<L, TC, 0, 1>(buf, tw, tr, tc, a.dir);
+  fft_panel<L, TC>(buf, tw, tr, tc, a.dir);
 
   if (a.mid != MID_NONE) {
     const uint8_t* mrow = a.mask + outer * a.mask_os;
     for (int r = tr; r < L; r += TR)
       if (mrow[(long long)r * a.mask_rs] == 0) buf[r * TC + tc] = make_float2(0.f, 0.f);
     __syncthreads();
-    if (a.mid == MID_MASK_IFFT) fft_stages<L, TC, 0, 1>(buf, tw, tr, tc, -a.dir);
+    if (a.mid == MID_MASK_IFFT) fft_panel<L, TC>(buf, tw, tr, tc, -a.dir);
   }
 
   if (a.epilogue == EPI_IMAGE) {
