@@ -121,14 +121,18 @@ int sketch_build(cs_ctx* ctx, const void* y, int V, int S, uint64_t seed, int t,
 
 /* Recon modes */
 enum { CS_RECON_FULL = 0, CS_RECON_SKETCH = 1, CS_RECON_SKETCH_LEARNED = 2 };
+/* Regularizers (Sec. 2.1): l1-wavelet g = lambda ||Psi x||_1, solved with
+ * FISTA; l2 (Tikhonov) g = lambda/2 ||x||^2, solved with conjugate
+ * gradients */
+enum { CS_REG_L1WAV = 0, CS_REG_L2 = 1 };
 
 typedef struct cs_cnn cs_cnn;
 
 typedef struct {
-  int mode;          /* CS_RECON_FULL: plain FISTA; CS_RECON_SKETCH: Algorithm 1 */
-  float lam;         /* l1-wavelet weight lambda */
-  int T;             /* FULL: FISTA iterations; SKETCH: outer iterations */
-  int K;             /* SKETCH: inner FISTA iterations per subproblem */
+  int mode;          /* CS_RECON_FULL: plain solver; CS_RECON_SKETCH: Algorithm 1 */
+  float lam;         /* regularization weight lambda */
+  int T;             /* FULL: solver iterations; SKETCH: outer iterations */
+  int K;             /* SKETCH: inner solver iterations per subproblem */
   int V, S;          /* sketch design (Sec. 2.3.3) */
   uint64_t seed;     /* sketch seed */
   int t0;            /* first outer index (resume: x_inout holds x^{t0}) */
@@ -138,6 +142,8 @@ typedef struct {
   int reuse_b;       /* non-zero: reuse b = A^H y from the previous call */
   const void* x_ref; /* device [D] or NULL: per-iteration distance reference */
   cs_cnn* cnn;       /* CS_RECON_SKETCH_LEARNED: the warm-start network (borrowed) */
+  int reg;           /* CS_REG_L1WAV (FISTA, the default) or CS_REG_L2 (CG; FULL
+                        and SKETCH modes only) */
 } cs_recon_params;
 
 typedef struct {
@@ -163,9 +169,14 @@ typedef struct {
   double ms_warm;
 } cs_recon_stats;
 
-/* Reconstruction (Algorithm 1 or plain FISTA) of x from data y on the
+/* Reconstruction (Algorithm 1 or the plain solver) of x from data y on the
  * operator bound by cs_set_operator.  y device [N][C]; x_inout device [D]:
- * x^{t0} on entry, the result on exit.  CS_RECON_SKETCH_LEARNED runs
+ * x^{t0} on entry, the result on exit.  With CS_REG_L2, FULL runs T CG
+ * iterations on (A^H A + lambda I) x = A^H y from x^{t0}, and SKETCH runs
+ * Algorithm 1 whose subproblem (Eq. 10 with g = lambda/2 ||x||^2) is the
+ * linear system (A_S^H A_S + lambda I) u = -(d^t + lambda x^t), solved by K
+ * CG iterations from u = 0, x^{t+1} = x^t + u; no step size is needed (alpha
+ * is reported as 0) and CG scalars are FP64 reductions.  CS_RECON_SKETCH_LEARNED runs
  * Algorithm 1 with each subproblem's FISTA started at
  * z0 = x^t + s_o CNN(x^t / s_x, d^t / s_d) (s_d = rms(d^t), s_o = alpha s_d,
  * s_x = rms(x^t) or s_o while x^t = 0) when the FP64 subproblem objective

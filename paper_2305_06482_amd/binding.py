@@ -26,6 +26,7 @@ CS_NONCART = 1
 CS_RECON_FULL = 0
 CS_RECON_SKETCH = 1
 CS_RECON_SKETCH_LEARNED = 2
+CS_REG_L1WAV, CS_REG_L2 = 0, 1
 
 EXPORTED = [
     "cs_create", "cs_destroy", "cs_last_error", "cs_set_operator", "sense_apply",
@@ -78,6 +79,7 @@ class ReconParams(ctypes.Structure):
         ("reuse_b", ctypes.c_int),
         ("x_ref", ctypes.c_void_p),
         ("cnn", ctypes.c_void_p),
+        ("reg", ctypes.c_int),
     ]
 
 
@@ -356,7 +358,10 @@ class Context:
         return smaps, lam, Uc, sg
 
     def recon_run(self, y, mode="sketch", lam=1e-3, T=10, K=5, V=2, S=2, seed=0, t0=1,
-                  step=0.0, n_pow=30, reuse_b=False, x=None, x_ref=None, cnn=None):
+                  step=0.0, n_pow=30, reuse_b=False, x=None, x_ref=None, cnn=None,
+                  reg="l1wav"):
+        """Algorithm 1 (mode "sketch", "learned") or the plain solver ("full")
+        with regularizer reg: "l1wav" (FISTA) or "l2" (conjugate gradients)."""
         self._data(y, self.C)
         if x is None:
             x = torch.zeros(self.shape, dtype=torch.complex64, device=self.device)
@@ -367,6 +372,7 @@ class Context:
         p.mode = {"sketch": CS_RECON_SKETCH, "full": CS_RECON_FULL,
                   "learned": CS_RECON_SKETCH_LEARNED}[mode]
         p.cnn = None if cnn is None else cnn._n.value
+        p.reg = {"l1wav": CS_REG_L1WAV, "l2": CS_REG_L2}[reg]
         p.lam = float(lam)
         p.T, p.K, p.V, p.S = int(T), int(K), int(V), int(S)
         p.seed = int(seed)

@@ -583,6 +583,48 @@ int inner_fista(cs_ctx* c, float2* x, int Ch, int K, float a, float tau_l,
   return CS_OK;
 }
 
+// K conjugate-gradient iterations on (A^H A + lam I) u = rhs, A^H A built
+// on `maps` (ncoil coils).  On entry u holds the start and r the right-hand
+// side; the residual r = rhs - M u is formed here (one extra apply unless
+// u_zero says u = 0).  CG scalars are FP64 reductions; p and q are work
+// vectors.  Returns the normal applies made in *napplies.
+int cg_solve(cs_ctx* c, const float2* maps, int ncoil, float lam, float2* u, bool u_zero,
+             float2* r, float2* p, float2* q, int K, int kind,
+             const std::function<int(int, const std::function<int()>&)>* timed,
+             long long* napplies) {
+  const long long D = c->D;
+  auto run = [&](const std::function<int()>& fn) { return timed ? (*timed)(kind, fn) : fn(); };
+  long long n = 0;
+  if (!u_zero) {
+    CS_TRY(run([&] { return op_normal(c, maps, ncoil, u, q); }));
+    ++n;
+    CS_TRY(vec_axpby(c, q, 1.f, q, lam, u, D));  // q = M u
+    CS_TRY(vec_axpby(c, r, 1.f, r, -1.f, q, D));
+  }
+  CS_TRY(vec_copy(c, p, r, D));
+  double rr[2];
+  CS_TRY(vec_dot(c, r, r, D, rr));
+  for (int k = 0; k < K; ++k) {
+    if (!(rr[0] > 0.0)) break;  // exact solution (or zero right-hand side)
+    CS_TRY(run([&] { return op_normal(c, maps, ncoil, p, q); }));
+    ++n;
+    CS_TRY(vec_axpby(c, q, 1.f, q, lam, p, D));
+    double pq[2];
+    CS_TRY(vec_dot(c, p, q, D, pq));
+    if (!(pq[0] > 0.0) || !std::isfinite(pq[0])) break;
+    const double alpha = rr[0] / pq[0];
+    CS_TRY(vec_axpby(c, u, 1.f, u, (float)alpha, p, D));
+    CS_TRY(vec_axpby(c, r, 1.f, r, (float)-alpha, q, D));
+    double rn[2];
+    CS_TRY(vec_dot(c, r, r, D, rn));
+    const double beta = rn[0] / rr[0];
+    CS_TRY(vec_axpby(c, p, 1.f, r, (float)beta, p, D));
+    rr[0] = rn[0];
+  }
+  *napplies = n;
+  return CS_OK;
+}
+
 }  // namespace cs
 
 using namespace cs;
@@ -789,6 +831,7 @@ int cs_cnn_collect(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_
   if (!c->have_op) return fail(c, CS_EINVAL, "cs_set_operator has not been called");
   if (!y_ || !p || !x_inout || !inputs || !targets) return fail(c, CS_EINVAL, "null argument");
   if (p->T < 1 || p->K < 1) return fail(c, CS_EINVAL, "iteration counts");
+  if (p->reg != CS_REG_L1WAV) return fail(c, CS_EINVAL, "pairs are collected for l1-wavelet only");
   const float2* y = (const float2*)y_;
   float2* x = (float2*)x_inout;
   const long long D = c->D;
@@ -831,6 +874,9 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
     return fail(c, CS_EINVAL, "recon mode");
   const bool learned = p->mode == CS_RECON_SKETCH_LEARNED;
   if (learned && !p->cnn) return fail(c, CS_EINVAL, "learned mode needs a network");
+  if (p->reg != CS_REG_L1WAV && p->reg != CS_REG_L2) return fail(c, CS_EINVAL, "regularizer");
+  const bool l2 = p->reg == CS_REG_L2;
+  if (l2 && learned) return fail(c, CS_EINVAL, "the learned warm start is for l1-wavelet only");
   if (p->T < 0 || (p->mode != CS_RECON_FULL && p->K < 1))
     return fail(c, CS_EINVAL, "iteration counts");
   if (st) st->n_warm_accepted = st->n_warm_rejected = 0;
@@ -864,15 +910,16 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
   const int n_pow = p->n_pow > 0 ? p->n_pow : 30;
   long long nfull = 0, nsk = 0, nprox = 0;
   double alpha = p->step;
+  if (l2) alpha = 0.0;  // CG needs no step size
   if (p->mode != CS_RECON_FULL) {
     CS_TRY(sketch_impl(c, y, p->V, p->S, p->seed, p->t0, 0, c->smaps, nullptr));
-    if (alpha <= 0) {
+    if (alpha <= 0 && !l2) {
       double L = 0;
       CS_TRY(power_iter(c, c->smaps, Ch, n_pow, &L));
       nsk += n_pow + 1;
       alpha = 1.0 / L;
     }
-  } else if (alpha <= 0) {
+  } else if (alpha <= 0 && !l2) {
     double L = 0;
     CS_TRY(power_iter(c, c->maps, C, n_pow, &L));
     nfull += n_pow + 1;
@@ -933,7 +980,66 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
     CS_HIP(c, hipEventRecord(evd[it], c->stream));
     return CS_OK;
   };
-  if (p->mode == CS_RECON_FULL) {
+  if (l2 && p->mode == CS_RECON_FULL) {
+    // CG on (A^H A + lam I) x = b, one iteration per record
+    float2* r = c->img[6];
+    float2* pd = c->img[2];
+    float2* q = c->img[5];
+    CS_TRY(vec_copy(c, r, b, D));
+    long long n = 0;
+    // the first call forms the residual; later calls continue the same CG
+    // (they are split only to record per-iteration progress)
+    double rr[2] = {0, 0};
+    for (int it = 0; it < p->T; ++it) {
+      if (it == 0) {
+        CS_TRY(cg_solve(c, c->maps, C, p->lam, x, false, r, pd, q, 1, 0, &timed_fn, &n));
+        nfull += n;
+        CS_TRY(vec_dot(c, r, r, D, rr));
+      } else if (rr[0] > 0.0) {
+        CS_TRY(timed(0, [&] { return op_normal(c, c->maps, C, pd, q); }));
+        ++nfull;
+        CS_TRY(vec_axpby(c, q, 1.f, q, p->lam, pd, D));
+        double pq[2];
+        CS_TRY(vec_dot(c, pd, q, D, pq));
+        if (pq[0] > 0.0 && std::isfinite(pq[0])) {
+          const double al = rr[0] / pq[0];
+          CS_TRY(vec_axpby(c, x, 1.f, x, (float)al, pd, D));
+          CS_TRY(vec_axpby(c, r, 1.f, r, (float)-al, q, D));
+          double rn[2];
+          CS_TRY(vec_dot(c, r, r, D, rn));
+          CS_TRY(vec_axpby(c, pd, 1.f, r, (float)(rn[0] / rr[0]), pd, D));
+          rr[0] = rn[0];
+        } else {
+          rr[0] = 0.0;
+        }
+      }
+      CS_TRY(record(it));
+    }
+  } else if (l2) {
+    // Algorithm 1 with g = lam/2 ||x||^2: the subproblem of Eq. 10 is the
+    // system (A_S^H A_S + lam I) u = -(d + lam x^t), K CG iterations from u = 0
+    float2* u = c->img[4];
+    float2* r = c->img[6];
+    float2* pd = c->img[2];
+    float2* q = c->img[5];
+    for (int it = 0; it < p->T; ++it) {
+      const int t = p->t0 + it;
+      CS_TRY(timed(0, [&] { return op_normal(c, c->maps, C, x, g); }));
+      ++nfull;
+      CS_TRY(vec_axpby(c, d, 1.f, g, -1.f, b, D));
+      if (it > 0)
+        CS_TRY(timed(3, [&] {
+          return sketch_impl(c, y, p->V, p->S, p->seed, t, 0, c->smaps, nullptr);
+        }));
+      CS_TRY(vec_axpby(c, r, -1.f, d, -p->lam, x, D));
+      CS_TRY(vec_fill(c, u, D, 0.f, 0.f));
+      long long n = 0;
+      CS_TRY(cg_solve(c, c->smaps, Ch, p->lam, u, true, r, pd, q, p->K, 1, &timed_fn, &n));
+      nsk += n;
+      CS_TRY(vec_axpby(c, x, 1.f, x, 1.f, u, D));
+      CS_TRY(record(it));
+    }
+  } else if (p->mode == CS_RECON_FULL) {
     // plain FISTA: g = A^H A z - b
     CS_TRY(vec_copy(c, z, x, D));
     double tau = 1.0;

@@ -136,7 +136,8 @@ int cs_batch_recon(cs_batch* b, const void* const* y, const cs_recon_params* p,
     cs_ctx* c = b->ctx[i];
     if (!y[i] || !x[i]) return bfail(b, CS_EINVAL, "null slice buffer");
     if (!c->have_op) return bfail(b, CS_EINVAL, "slice without an operator");
-    if (p[i].mode != CS_RECON_SKETCH || p[i].T != T || p[i].K != K || K < 1 || T < 0)
+    if (p[i].mode != CS_RECON_SKETCH || p[i].reg != CS_REG_L1WAV || p[i].T != T ||
+        p[i].K != K || K < 1 || T < 0)
       return bfail(b, CS_EINVAL, "every slice needs SKETCH mode and the same T and K");
   }
   drop_graph(b);

@@ -247,6 +247,11 @@ int sketch_impl(cs_ctx* c, const float2* y, int V, int S, uint64_t seed, int t, 
 int inner_fista(cs_ctx* c, float2* x, int Ch, int K, float a, float tau_l,
                 const std::function<int(int, const std::function<int()>&)>* timed,
                 const float2* start);
+// K CG iterations on (A^H A + lam I) u = rhs (r holds rhs on entry)
+int cg_solve(cs_ctx* c, const float2* maps, int ncoil, float lam, float2* u, bool u_zero,
+             float2* r, float2* p, float2* q, int K, int kind,
+             const std::function<int(int, const std::function<int()>&)>* timed,
+             long long* napplies);
 
 // cnn.hip: learned warm start
 int cnn_pack_input(cs_ctx* c, const float2* x, const float2* d, float sx, float sd,
