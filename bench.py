@@ -275,6 +275,85 @@ def cartesian_tta(p, args, log):
     return res
 
 
+def gfactor_bench(args, log, n=256, C=8, accel=3, trials=60, lam=1e-2, sigma=1e-2,
+                  T_full=60, T=10, K=20, designs=((3, 1), (2, 2)), seed=8000):
+    """Monte-Carlo inverse g-factor of l2 reconstructions (Sec. 3.2.2):
+    regular R = 3 Cartesian sampling, `trials` noise realisations, full-coil
+    CG against Algorithm 1 with CG inner solves.  g = sd_R / (sd_full sqrt(R))
+    per pixel, sd_full from fully sampled reconstructions of the same noise
+    level; the sketch design (PCA basis) is fixed by the first trial, so every
+    reconstruction is the same linear map of the data."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2305_06482_amd import Context
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    shape = (n, n)
+    x = torch.from_numpy(synth.phantom(shape, seed)).to(torch.complex64).to(dev)
+    maps = torch.from_numpy(synth.coil_maps(shape, C, seed + 1)).to(torch.complex64).to(dev)
+    mask_u = synth.mask_regular(n, n, accel=accel)
+    R = mask_u.size / mask_u.sum()
+    ctxs = {}
+    for name, mk in (("under", mask_u), ("full", np.ones(shape, np.uint8))):
+        c = Context(shape, C, "cart", wav_levels=4)
+        c.set_operator(maps, mask=torch.from_numpy(mk).to(dev))
+        ctxs[name] = (c, torch.from_numpy(mk).to(torch.float32).to(dev)[..., None],
+                      c.sense_apply(maps, x))
+    gen = torch.Generator(device=dev).manual_seed(seed)
+    runs = {"full_coil": None, **{f"sketch_V{V}S{S}": (V, S) for V, S in designs}}
+    acc = {k: [torch.zeros(shape, dtype=torch.complex128, device=dev),
+               torch.zeros(shape, dtype=torch.float64, device=dev), 0.0] for k in runs}
+    acc["fully_sampled"] = [torch.zeros(shape, dtype=torch.complex128, device=dev),
+                            torch.zeros(shape, dtype=torch.float64, device=dev), 0.0]
+
+    def add(key, xr, ms):
+        a = acc[key]
+        a[0] += xr.to(torch.complex128)
+        a[1] += xr.abs().to(torch.float64) ** 2
+        a[2] += ms
+
+    for tr in range(trials):
+        for name in ("under", "full"):
+            c, m, y0 = ctxs[name]
+            nz = torch.randn(shape + (C, 2), generator=gen, device=dev) * (sigma / math.sqrt(2))
+            y = y0 + torch.view_as_complex(nz.contiguous()) * m
+            if name == "full":
+                r = c.recon_run(y, mode="full", reg="l2", lam=lam, T=T_full)
+                add("fully_sampled", r.x, r.total_ms)
+                continue
+            for key, vs in runs.items():
+                if vs is None:
+                    r = c.recon_run(y, mode="full", reg="l2", lam=lam, T=T_full)
+                else:
+                    r = c.recon_run(y, mode="sketch", reg="l2", lam=lam, T=T, K=K, V=vs[0],
+                                    S=vs[1], seed=seed)
+                add(key, r.x, r.total_ms + r.prep_ms)
+    torch.cuda.synchronize()
+
+    def sd(key):
+        a = acc[key]
+        mean = a[0] / trials
+        return ((a[1] / trials - mean.abs() ** 2).clamp_min(0) * trials / (trials - 1)).sqrt()
+
+    support = x.abs() > 0.05 * x.abs().max()
+    sd_ref = sd("fully_sampled")
+    res = {"shape": list(shape), "coils": C, "R": round(float(R), 3), "trials": trials,
+           "lam": lam, "sigma": sigma, "T_full": T_full, "T": T, "K": K}
+    for key in runs:
+        inv = (sd_ref * math.sqrt(R) / sd(key))[support].cpu().numpy()
+        res[key] = {"inv_g_mean": float(np.mean(inv)), "inv_g_p5": float(np.percentile(inv, 5)),
+                    "inv_g_min": float(np.min(inv)),
+                    "ms_per_recon": acc[key][2] / trials}
+    res["wall_s"] = round(time.time() - t0, 1)
+    for c, *_ in ctxs.values():
+        c.close()
+    log(f"inverse g-factor ({trials} trials, {n}x{n}, {C} coils, R={R:.2f}): " +
+        ", ".join(f"{k}: mean {v['inv_g_mean']:.3f} p5 {v['inv_g_p5']:.3f}, "
+                  f"{v['ms_per_recon']:.2f} ms" for k, v in res.items() if isinstance(v, dict)))
+    return res
+
+
 def batched_bench(args, log, T=3, K=5):
     """The batched workload: 64 independent 2D golden-angle radial slices of
     uneven matrix size, spoke count, coil count and sketch size, each on its
@@ -372,6 +451,8 @@ def main():
     ap.add_argument("--small", action="store_true", help="48^3 instance (quick check)")
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-accuracy runs")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-slice batch")
+    ap.add_argument("--no-gfactor", action="store_true",
+                    help="skip the Monte-Carlo inverse g-factor of l2 reconstructions")
     ap.add_argument("--tta-ref-iters", type=int, default=2000)
     ap.add_argument("--tta-chunk", type=int, default=100)
     ap.add_argument("--tta-full-iters", type=int, default=1200)
@@ -532,6 +613,13 @@ def main():
     out["precision"] = precision_report(ctx, p, Ch, cpu_ref, log)
     if not args.no_batched and not args.small:
         out["batched_radial"] = batched_bench(args, log)
+    if not args.no_gfactor and not args.small:
+        # lam = 1e-2: every design converges and keeps the full-coil
+        # g-factor; lam = 1e-3: the R = 3 system is ill conditioned and
+        # small-C^ designs stop converging
+        out["l2_inverse_gfactor"] = {
+            f"lam{lam:g}": gfactor_bench(args, log, lam=lam, designs=((3, 1), (2, 2), (6, 1)))
+            for lam in (1e-2, 1e-3)}
     if not args.no_tta:
         log("time-to-accuracy runs")
         tta = {"thresholds": list(TTA_THRESHOLDS)}
