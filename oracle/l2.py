@@ -57,7 +57,7 @@ def l2_full(normal_fn, b, x0, lam, n_iter):
 
 
 def l2_sketch(normal_maps_fn, maps, y, dcf, b, x0, V, S, seed, T, K, lam, t0=1,
-              callback=None):
+              callback=None, dist="rademacher"):
     """Algorithm 1 with g = lam/2 ||x||^2 and K-iteration CG inner solves.
     ``normal_maps_fn(x, maps)`` applies A^H A built on the given maps.
     Returns (x^T, state)."""
@@ -65,7 +65,7 @@ def l2_sketch(normal_maps_fn, maps, y, dcf, b, x0, V, S, seed, T, K, lam, t0=1,
     x = np.array(x0, dtype=np.complex128, copy=True)
     for t in range(t0, t0 + T):
         d = normal_maps_fn(x, maps) - b
-        mt = st.maps_for(V, S, seed, t)
+        mt = st.maps_for(V, S, seed, t, dist)
         u = cg(lambda v: normal_maps_fn(v, mt) + lam * v, -(d + lam * x),
                np.zeros_like(x), K)
         x = x + u

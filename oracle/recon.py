@@ -93,12 +93,12 @@ class SketchState:
         self.lam, self.U = sk.pca(self.R)
         self.vmaps = sk.virtual_maps(maps, self.U)
 
-    def maps_for(self, V, S, seed, t):
-        return sk.sketch_for_iteration(self.vmaps, V, S, seed, t)[0]
+    def maps_for(self, V, S, seed, t, dist="rademacher"):
+        return sk.sketch_for_iteration(self.vmaps, V, S, seed, t, dist)[0]
 
 
 def coil_sketch(normal_maps_fn, maps, y, dcf, b, x0, V, S, seed, T, K, lam,
-                alpha=None, levels=4, n_pow=30, callback=None, t0=1):
+                alpha=None, levels=4, n_pow=30, callback=None, t0=1, dist="rademacher"):
     """Algorithm 1 with FISTA inner solves.
 
     ``normal_maps_fn(x, maps)`` applies A^H A built on the given maps.
@@ -106,13 +106,13 @@ def coil_sketch(normal_maps_fn, maps, y, dcf, b, x0, V, S, seed, T, K, lam,
     """
     st = SketchState(maps, y, dcf)
     if alpha is None:
-        m1 = st.maps_for(V, S, seed, 1)
+        m1 = st.maps_for(V, S, seed, 1, dist)
         L = power_iteration(lambda v: normal_maps_fn(v, m1), x0.shape, n_pow)
         alpha = 1.0 / L
     x = np.array(x0, dtype=np.complex128, copy=True)
     for t in range(t0, t0 + T):
         d = normal_maps_fn(x, maps) - b
-        mt = st.maps_for(V, S, seed, t)
+        mt = st.maps_for(V, S, seed, t, dist)
         x = sketched_subproblem(lambda v: normal_maps_fn(v, mt), d, x, alpha, lam, K, levels)
         if callback is not None:
             callback(t, x)

@@ -22,6 +22,15 @@ Readings:
     ctr = (t << 32) | (a * (C - V) + b).  SplitMix64 is Steele, Lea and Flood,
     "Fast splittable pseudorandom number generators", OOPSLA 2014: the n-th
     output is mix(seed + n * 0x9E3779B97F4A7C15) with the "mix13" finaliser.
+  * Gaussian entries (the other distribution of Sec. 3.2): "sigma = 1/S" is
+    read as variance 1/S, the scaling that gives E[S~^T S~] = I like the
+    Rademacher draw.  Entry e = a (C - V) + b takes outputs n1 = c + 1 and
+    n2 = c + 2 with c = (t << 32) | 2e, the uniforms
+    u1 = ((z1 >> 11) + 1) 2^-53 in (0, 1] and u2 = (z2 >> 11) 2^-53, and the
+    Box-Muller value sqrt(-2 ln u1) cos(2 pi u2) (Box and Muller, 1958).
+  * S = 0 with V < C keeps only the V high-energy virtual coils (coil
+    compression inside the subproblem), the design the paper reports to make
+    Algorithm 1 diverge.
 """
 from __future__ import annotations
 
@@ -93,12 +102,28 @@ def virtual_data(y: np.ndarray, U: np.ndarray) -> np.ndarray:
     return y @ np.conj(U)
 
 
-def sketch_matrix(V: int, S: int, C: int, signs: np.ndarray | None) -> np.ndarray:
-    """S~ = blkdiag(I_V, signs / sqrt(S)), shape (V + S) x C."""
+def gaussian(seed: int, t: int, S: int, CmV: int) -> np.ndarray:
+    """Unit-variance normal entries (float64) of the S x (C - V) block for
+    outer iteration t (Box-Muller on two SplitMix64 uniforms per entry)."""
+    out = np.empty((S, CmV), dtype=np.float64)
+    for a in range(S):
+        for b in range(CmV):
+            c = ((t & 0xFFFFFFFF) << 32) | (2 * (a * CmV + b))
+            z1 = splitmix64_output(seed, c + 1)
+            z2 = splitmix64_output(seed, c + 2)
+            u1 = ((z1 >> 11) + 1) * 2.0 ** -53
+            u2 = (z2 >> 11) * 2.0 ** -53
+            out[a, b] = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    return out
+
+
+def sketch_matrix(V: int, S: int, C: int, entries: np.ndarray | None) -> np.ndarray:
+    """S~ = blkdiag(I_V, entries / sqrt(S)), shape (V + S) x C; entries are
+    the +-1 signs or the unit-variance normal values of the random block."""
     St = np.zeros((V + S, C))
     St[:V, :V] = np.eye(V)
     if S > 0:
-        St[V:, V:] = np.asarray(signs, dtype=np.float64) / np.sqrt(S)
+        St[V:, V:] = np.asarray(entries, dtype=np.float64) / np.sqrt(S)
     return St
 
 
@@ -107,7 +132,8 @@ def sketched_maps(vmaps: np.ndarray, St: np.ndarray) -> np.ndarray:
     return vmaps @ St.T
 
 
-def sketch_for_iteration(vmaps, V, S, seed, t):
+def sketch_for_iteration(vmaps, V, S, seed, t, dist="rademacher"):
     C = vmaps.shape[-1]
-    signs = rademacher(seed, t, S, C - V) if S > 0 else None
-    return sketched_maps(vmaps, sketch_matrix(V, S, C, signs)), signs
+    draw = rademacher if dist == "rademacher" else gaussian
+    entries = draw(seed, t, S, C - V) if S > 0 else None
+    return sketched_maps(vmaps, sketch_matrix(V, S, C, entries)), entries

@@ -109,3 +109,52 @@ def test_sketch_matrix_structure():
     assert np.array_equal(St[:2, :2], np.eye(2))
     assert np.all(St[:2, 2:] == 0) and np.all(St[2:, :2] == 0)
     assert np.allclose(np.abs(St[2:, 2:]), 1 / np.sqrt(3))
+
+
+def test_gaussian_draw_is_standard_normal():
+    from scipy import stats
+    vals = np.concatenate([sk.gaussian(11, t, 32, 64).ravel() for t in range(1, 9)])
+    assert vals.size == 8 * 32 * 64
+    assert abs(vals.mean()) < 0.03 and abs(vals.var() - 1.0) < 0.04
+    assert stats.kstest(vals, "norm").pvalue > 1e-3
+    # different outer iterations and seeds draw different blocks
+    assert not np.array_equal(sk.gaussian(11, 1, 2, 3), sk.gaussian(11, 2, 2, 3))
+    assert not np.array_equal(sk.gaussian(11, 1, 2, 3), sk.gaussian(12, 1, 2, 3))
+
+
+def test_gaussian_sketch_is_isotropic_in_expectation():
+    # E[S~^T S~] = I with variance-1/S entries (averaged over many draws)
+    V, S, C = 2, 3, 8
+    acc = np.zeros((C, C))
+    n = 3000
+    for t in range(1, n + 1):
+        St = sk.sketch_matrix(V, S, C, sk.gaussian(5, t, S, C - V))
+        acc += St.T @ St
+    assert np.max(np.abs(acc / n - np.eye(C))) < 0.1
+
+
+def test_s0_diverges_where_s1_converges():
+    # Sec. 3.2 reports that V = C^ (S = 0, coil compression inside the
+    # subproblem) makes the sketched iteration diverge while S >= 1 designs
+    # converge: l2, C^ = 4 of 8 coils
+    from oracle import l2
+    shape, C, lam = (32, 32), 8, 1e-2
+    x = synth.phantom(shape, 21)
+    maps = synth.coil_maps(shape, C, 22)
+    mask = synth.mask_1d_vd(32, 32, 23, n_center=6, accel=2)
+    y = cart.forward(x, maps, mask) + 1e-3 * synth.complex_noise(shape + (C,), 1.0, 24) * \
+        mask[..., None]
+    b = cart.adjoint(y, maps, mask)
+    nfn = lambda v, m: cart.normal(v, m, mask)
+    ref = l2.l2_full(lambda v: cart.normal(v, maps, mask), b, np.zeros(shape, complex), lam, 300)
+    err = {}
+    for V, S, dist in ((4, 0, "rademacher"), (3, 1, "rademacher"), (3, 1, "gaussian")):
+        e = []
+        l2.l2_sketch(nfn, maps, y.reshape(-1, C), None, b, np.zeros(shape, complex), V, S, 3, 15,
+                     50, lam, dist=dist,
+                     callback=lambda t, xx: e.append(np.linalg.norm(xx - ref) / np.linalg.norm(ref)))
+        err[(V, S, dist)] = e
+    e0 = err[(4, 0, "rademacher")]
+    assert e0[-1] > 3 * min(e0)  # moves away from the minimizer
+    for key in ((3, 1, "rademacher"), (3, 1, "gaussian")):
+        assert err[key][-1] < 1e-3, (key, err[key])
