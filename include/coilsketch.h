@@ -112,12 +112,26 @@ int normal_apply(cs_ctx* ctx, const void* maps, int ncoil, const void* x, void* 
  *   smaps   device [D][V+S] output
  *   eig     host [C] float64 (may be NULL): lambda
  *   U_out   host [C][C] complex128 row-major, column j = eigenvector j (may be NULL)
- *   signs   host [S][C-V] int8 (may be NULL): the draw.  Synchronises when any
- *           host output is requested.
- * Requires V >= 0, S >= 0, 0 < V + S <= C, and S > 0 or V = C. */
+ *   signs   host [S][C-V] int8 (may be NULL): the Rademacher draw (left
+ *           untouched under the Gaussian distribution).  Synchronises when
+ *           any host output is requested.
+ * Requires V >= 0, S >= 0 and 0 < V + S <= C.  S = 0 with V < C keeps only
+ * the V high-energy virtual coils (coil compression inside the subproblem;
+ * Sec. 3.2 reports that Algorithm 1 then diverges).  The random block's
+ * distribution is set per context by cs_set_sketch_dist. */
 int sketch_build(cs_ctx* ctx, const void* y, int V, int S, uint64_t seed, int t,
                  int refresh, void* smaps, double* eig, double* U_out,
                  int8_t* signs);
+
+/* Distribution of the random block (Sec. 3.2): Rademacher (the default) or
+ * Gaussian with variance 1/S (values / sqrt(S) with unit-variance values;
+ * E[S~^T S~] = I for both).  Gaussian entry e = a (C-V) + b of outer
+ * iteration t: SplitMix64(seed) outputs n1 = c + 1, n2 = c + 2 with
+ * c = (t << 32) | 2e, u1 = ((z1 >> 11) + 1) 2^-53, u2 = (z2 >> 11) 2^-53 and
+ * value sqrt(-2 ln u1) cos(2 pi u2) (Box-Muller).  Applies to later
+ * sketch_build and recon_run calls on this context. */
+enum { CS_SKETCH_RADEMACHER = 0, CS_SKETCH_GAUSSIAN = 1 };
+int cs_set_sketch_dist(cs_ctx* ctx, int dist);
 
 /* Recon modes */
 enum { CS_RECON_FULL = 0, CS_RECON_SKETCH = 1, CS_RECON_SKETCH_LEARNED = 2 };

@@ -27,6 +27,7 @@ CS_RECON_FULL = 0
 CS_RECON_SKETCH = 1
 CS_RECON_SKETCH_LEARNED = 2
 CS_REG_L1WAV, CS_REG_L2 = 0, 1
+CS_SKETCH_RADEMACHER, CS_SKETCH_GAUSSIAN = 0, 1
 
 EXPORTED = [
     "cs_create", "cs_destroy", "cs_last_error", "cs_set_operator", "sense_apply",
@@ -34,7 +35,7 @@ EXPORTED = [
     "cs_dwt", "cs_idwt", "cs_coil_mix", "cs_dot", "cs_power_iteration", "cs_grid_shape",
     "cs_profile_enable", "cs_profile_read", "cs_batch_create", "cs_batch_destroy",
     "cs_batch_last_error", "cs_batch_recon", "cs_set_spread_cfg", "cs_autotune_spread",
-    "cs_set_interp_cfg",
+    "cs_set_interp_cfg", "cs_set_sketch_dist",
     "cs_cnn_create", "cs_cnn_destroy", "cs_cnn_last_error", "cs_cnn_num_params",
     "cs_cnn_get_params", "cs_cnn_set_params", "cs_cnn_forward", "cs_cnn_loss_grad",
     "cs_cnn_train_step", "cs_cnn_collect",
@@ -156,6 +157,7 @@ def load() -> ctypes.CDLL:
                                    ctypes.POINTER(BatchStats)]
     lib.cs_set_spread_cfg.argtypes = [vp, ci]
     lib.cs_set_interp_cfg.argtypes = [vp, ci]
+    lib.cs_set_sketch_dist.argtypes = [vp, ci]
     lib.cs_autotune_spread.argtypes = [vp, vp, ci, ci, ctypes.POINTER(ci), vp]
     lib.cs_cnn_create.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(vp)]
     lib.cs_cnn_destroy.argtypes = [vp]
@@ -494,6 +496,13 @@ class Context:
     def set_spread_cfg(self, cfg):
         """Select a spreading work-group shape (0 .. SPREAD_NCFG - 1)."""
         self._check(self.lib.cs_set_spread_cfg(self._ctx, int(cfg)), "cs_set_spread_cfg")
+
+    def set_sketch_dist(self, dist):
+        """Distribution of the sketch's random block: "rademacher" or
+        "gaussian" (variance 1/S), for later sketch_build / recon_run calls."""
+        self._check(self.lib.cs_set_sketch_dist(
+            self._ctx, {"rademacher": CS_SKETCH_RADEMACHER, "gaussian": CS_SKETCH_GAUSSIAN}[dist]),
+            "cs_set_sketch_dist")
 
     def set_interp_cfg(self, cfg):
         """Select the interpolation variant: 0 global-memory gather, 1 LDS

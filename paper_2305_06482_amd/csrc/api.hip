@@ -30,6 +30,24 @@ void rademacher(uint64_t seed, int t, int S, int cols, std::vector<int8_t>& out)
       out[(size_t)a * cols + b] = (z >> 63) ? -1 : 1;
     }
 }
+
+// Gaussian block of outer iteration t (unit variance): entry e = a cols + b
+// takes outputs c + 1 and c + 2, c = (t << 32) | 2e, as uniforms
+// u1 in (0, 1] and u2 in [0, 1), and the Box-Muller value
+// sqrt(-2 ln u1) cos(2 pi u2).
+void gaussian(uint64_t seed, int t, int S, int cols, std::vector<double>& out) {
+  out.resize((size_t)S * cols);
+  for (int a = 0; a < S; ++a)
+    for (int b = 0; b < cols; ++b) {
+      const uint64_t e = (uint64_t)(a * cols + b);
+      const uint64_t ctr = ((uint64_t)(uint32_t)t << 32) | (2 * e);
+      const uint64_t z1 = splitmix64_mix(seed + (ctr + 1) * 0x9E3779B97F4A7C15ULL);
+      const uint64_t z2 = splitmix64_mix(seed + (ctr + 2) * 0x9E3779B97F4A7C15ULL);
+      const double u1 = (double)((z1 >> 11) + 1) * 0x1.0p-53;
+      const double u2 = (double)(z2 >> 11) * 0x1.0p-53;
+      out[(size_t)e] = std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
+    }
+}
 }  // namespace
 
 namespace cs {
@@ -501,8 +519,8 @@ int power_iter(cs_ctx* c, const float2* maps, int ncoil, int n_iter, double* L) 
 int sketch_impl(cs_ctx* c, const float2* y, int V, int S, uint64_t seed, int t, int refresh,
                 float2* smaps, std::vector<int8_t>* signs_out) {
   const int C = c->C;
-  if (V < 0 || S < 0 || V + S < 1 || V + S > C || (S == 0 && V != C))
-    return fail(c, CS_EINVAL, "sketch sizes: need 0 < V + S <= C and S > 0 unless V = C");
+  if (V < 0 || S < 0 || V + S < 1 || V + S > C)
+    return fail(c, CS_EINVAL, "sketch sizes: need V >= 0, S >= 0 and 0 < V + S <= C");
   if (!c->have_U || refresh) {
     if (!y) return fail(c, CS_EINVAL, "y is required for the first sketch");
     CS_TRY(covariance_eig(c, y));
@@ -523,12 +541,19 @@ int sketch_impl(cs_ctx* c, const float2* y, int V, int S, uint64_t seed, int t, 
     CS_TRY(coil_mix(c, c->vmaps, C, 0, V, I.data(), V, smaps, Ch, 0, 1.0f));
   }
   std::vector<int8_t> sg;
-  if (S > 0) {
+  if (S > 0 && V < C) {
     const int cols = C - V;
-    rademacher(seed, t, S, cols, sg);
     std::vector<double> R((size_t)2 * S * cols, 0.0);
-    for (int a = 0; a < S; ++a)
-      for (int b = 0; b < cols; ++b) R[2 * (a * cols + b)] = (double)sg[(size_t)a * cols + b];
+    if (c->sketch_dist == CS_SKETCH_GAUSSIAN) {
+      std::vector<double> gv;
+      gaussian(seed, t, S, cols, gv);
+      for (int a = 0; a < S; ++a)
+        for (int b = 0; b < cols; ++b) R[2 * (a * cols + b)] = gv[(size_t)a * cols + b];
+    } else {
+      rademacher(seed, t, S, cols, sg);
+      for (int a = 0; a < S; ++a)
+        for (int b = 0; b < cols; ++b) R[2 * (a * cols + b)] = (double)sg[(size_t)a * cols + b];
+    }
     CS_TRY(coil_mix(c, c->vmaps, C, V, cols, R.data(), S, smaps, Ch, V,
                     (float)(1.0 / std::sqrt((double)S))));
   }
@@ -737,6 +762,14 @@ int sketch_build(cs_ctx* c, const void* y, int V, int S, uint64_t seed, int t, i
   if (U_out) std::memcpy(U_out, c->U.data(), sizeof(double) * 2 * c->C * c->C);
   if (signs && !sg.empty()) std::memcpy(signs, sg.data(), sg.size());
   if (eig || U_out || signs) CS_HIP(c, hipStreamSynchronize(c->stream));
+  return CS_OK;
+}
+
+int cs_set_sketch_dist(cs_ctx* c, int dist) {
+  if (!c) return CS_EINVAL;
+  if (dist != CS_SKETCH_RADEMACHER && dist != CS_SKETCH_GAUSSIAN)
+    return fail(c, CS_EINVAL, "sketch distribution");
+  c->sketch_dist = dist;
   return CS_OK;
 }
 

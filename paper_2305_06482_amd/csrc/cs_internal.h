@@ -115,6 +115,7 @@ struct cs_ctx {
   size_t partial_elems = 0;       // float2 capacity of `partial`
   int spread_cfg = 0;             // spread work-group shape (see launch_spread)
   int interp_cfg = 1;             // interpolation: 0 per-sample gather, 1/2 LDS tiles
+  int sketch_dist = 0;            // CS_SKETCH_RADEMACHER or CS_SKETCH_GAUSSIAN
 
   // work buffers
   float2* gridA = nullptr;        // M * kCoilChunk
