@@ -354,6 +354,87 @@ def gfactor_bench(args, log, n=256, C=8, accel=3, trials=60, lam=1e-2, sigma=1e-
     return res
 
 
+def design_ablation(args, log, n=256, C=8, seeds=20, chats=(3, 4), T=10, K=10, lam=1e-3,
+                    T_base=300, seed_base=8100):
+    """Sketching-matrix design (Sec. 3.2.1) on a synthetic 2D radial slice
+    (R = 2, 8 coils, l1-wavelet): for C^ in chats, V = 0..C^ (S = C^ - V) and
+    Rademacher / Gaussian entries, `seeds` runs of Algorithm 1 with T outer
+    and K inner iterations; objective and NRMSE against the phantom, each
+    normalised by those of the full-coil FISTA baseline (T_base
+    iterations)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2305_06482_amd import Context, CSError
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    shape = (n, n)
+    spokes = int(round(math.pi / 2 * n / 2))  # half the Nyquist spoke count: R = 2
+    coords = synth.radial_traj(n, spokes)
+    dcf = synth.radial_dcf(coords, n)
+    xt = torch.from_numpy(synth.phantom(shape, seed_base)).to(torch.complex64).to(dev)
+    maps = torch.from_numpy(synth.coil_maps(shape, C, seed_base + 1)).to(torch.complex64).to(dev)
+    ctx = Context(shape, C, "noncart", nsamp=coords.shape[0], wav_levels=4)
+    w = torch.from_numpy(dcf).to(torch.float32).to(dev)
+    ctx.set_operator(maps, coords=torch.from_numpy(coords).to(torch.float32).to(dev), dcf=w)
+    noise = torch.from_numpy(synth.complex_noise((coords.shape[0], C), 1e-3, seed_base + 2))
+    y = ctx.sense_apply(maps, xt) + noise.to(torch.complex64).to(dev) * \
+        w.sqrt()[:, None].to(torch.complex64)
+
+    def metrics(x):
+        r = ctx.sense_apply(maps, x) - y
+        obj = 0.5 * float((r.abs().double() ** 2).sum()) + \
+            lam * float(ctx.dwt(x).abs().double().sum())
+        nr = float((x - xt).abs().double().norm() / xt.abs().double().norm())
+        return obj, nr
+
+    base = ctx.recon_run(y, mode="full", lam=lam, T=T_base)
+    f0, e0 = metrics(base.x)
+    res = {"shape": list(shape), "coils": C, "spokes": spokes, "seeds": seeds, "T": T, "K": K,
+           "lam": lam, "baseline": {"objective": f0, "nrmse": e0, "iterations": T_base}}
+    for ch in chats:
+        for V in range(ch + 1):
+            S = ch - V
+            for dist in (("rademacher", "gaussian") if S > 0 else ("none",)):
+                if dist != "none":
+                    ctx.set_sketch_dist(dist)
+                fs, es, diverged = [], [], 0
+                runs = seeds if S > 0 else 1
+                for sd in range(runs):
+                    try:
+                        r = ctx.recon_run(y, mode="sketch", lam=lam, T=T, K=K, V=V, S=S,
+                                          seed=seed_base + 17 * sd)
+                    except CSError:  # the library stops a run whose iterate overflows
+                        diverged += 1
+                        continue
+                    f, e = metrics(r.x)
+                    if not (math.isfinite(f) and f < 1e6 * f0):
+                        diverged += 1
+                        continue
+                    fs.append(f / f0)
+                    es.append(e / e0)
+                fs, es = np.array(fs), np.array(es)
+                ok = fs.size > 0
+                res[f"C{ch}_V{V}_S{S}_{dist}"] = {
+                    "objective_rel_median": float(np.median(fs)) if ok else None,
+                    "nrmse_rel_median": float(np.median(es)) if ok else None,
+                    "objective_rel_mean": float(np.mean(fs)) if ok else None,
+                    "objective_rel_std": float(np.std(fs)) if ok else None,
+                    "nrmse_rel_mean": float(np.mean(es)) if ok else None,
+                    "nrmse_rel_std": float(np.std(es)) if ok else None,
+                    "runs": runs, "diverged": diverged}
+    ctx.set_sketch_dist("rademacher")
+    ctx.close()
+    res["wall_s"] = round(time.time() - t0, 1)
+    log("design ablation (objective / baseline: median, mean +- std): " + ", ".join(
+        (f"{k}: median {v['objective_rel_median']:.4f}, "
+         f"{v['objective_rel_mean']:.4f}+-{v['objective_rel_std']:.4f}"
+         if v["objective_rel_mean"] is not None else f"{k}: diverged") +
+        (f" ({v['diverged']}/{v['runs']} diverged)" if v["diverged"] else "")
+        for k, v in res.items() if isinstance(v, dict) and "runs" in v))
+    return res
+
+
 def batched_bench(args, log, T=3, K=5):
     """The batched workload: 64 independent 2D golden-angle radial slices of
     uneven matrix size, spoke count, coil count and sketch size, each on its
@@ -451,6 +532,8 @@ def main():
     ap.add_argument("--small", action="store_true", help="48^3 instance (quick check)")
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-accuracy runs")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-slice batch")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the sketching-matrix design ablation (2D radial)")
     ap.add_argument("--no-gfactor", action="store_true",
                     help="skip the Monte-Carlo inverse g-factor of l2 reconstructions")
     ap.add_argument("--tta-ref-iters", type=int, default=2000)
@@ -613,6 +696,8 @@ def main():
     out["precision"] = precision_report(ctx, p, Ch, cpu_ref, log)
     if not args.no_batched and not args.small:
         out["batched_radial"] = batched_bench(args, log)
+    if not args.no_ablation and not args.small:
+        out["sketch_design_ablation"] = design_ablation(args, log)
     if not args.no_gfactor and not args.small:
         # lam = 1e-2: every design converges and keeps the full-coil
         # g-factor; lam = 1e-3: the R = 3 system is ill conditioned and
