@@ -137,8 +137,10 @@ int cs_set_sketch_dist(cs_ctx* ctx, int dist);
 enum { CS_RECON_FULL = 0, CS_RECON_SKETCH = 1, CS_RECON_SKETCH_LEARNED = 2 };
 /* Regularizers (Sec. 2.1): l1-wavelet g = lambda ||Psi x||_1, solved with
  * FISTA; l2 (Tikhonov) g = lambda/2 ||x||^2, solved with conjugate
- * gradients */
-enum { CS_REG_L1WAV = 0, CS_REG_L2 = 1 };
+ * gradients; l1 total variation g = lambda ||T x||_1 (T the periodic
+ * first-order differences, every component's complex modulus), solved with
+ * PDHG whose data-consistency step is a CG solve */
+enum { CS_REG_L1WAV = 0, CS_REG_L2 = 1, CS_REG_TV = 2 };
 
 typedef struct cs_cnn cs_cnn;
 
@@ -156,8 +158,10 @@ typedef struct {
   int reuse_b;       /* non-zero: reuse b = A^H y from the previous call */
   const void* x_ref; /* device [D] or NULL: per-iteration distance reference */
   cs_cnn* cnn;       /* CS_RECON_SKETCH_LEARNED: the warm-start network (borrowed) */
-  int reg;           /* CS_REG_L1WAV (FISTA, the default) or CS_REG_L2 (CG; FULL
-                        and SKETCH modes only) */
+  int reg;           /* CS_REG_L1WAV (FISTA, the default), CS_REG_L2 (CG) or
+                        CS_REG_TV (PDHG); l2 and TV: FULL and SKETCH modes only */
+  int n_cg;          /* CS_REG_TV: CG iterations per PDHG data-consistency step
+                        (<= 0 selects 5) */
 } cs_recon_params;
 
 typedef struct {
@@ -190,7 +194,14 @@ typedef struct {
  * Algorithm 1 whose subproblem (Eq. 10 with g = lambda/2 ||x||^2) is the
  * linear system (A_S^H A_S + lambda I) u = -(d^t + lambda x^t), solved by K
  * CG iterations from u = 0, x^{t+1} = x^t + u; no step size is needed (alpha
- * is reported as 0) and CG scalars are FP64 reductions.  CS_RECON_SKETCH_LEARNED runs
+ * is reported as 0) and CG scalars are FP64 reductions.  With CS_REG_TV,
+ * FULL runs T PDHG iterations (Chambolle-Pock, theta = 1,
+ * tau = sigma = 1/sqrt(4 ndim), dual variable starting at 0):
+ *   u <- clip(u + sigma T xbar, lambda),  v = x - tau T^H u,
+ *   x <- solution of (A^H A + I/tau) x = A^H y + v/tau (n_cg CG iterations
+ *        warm-started at x),  xbar = 2 x_new - x_old;
+ * SKETCH runs Algorithm 1 with K such PDHG iterations per subproblem, whose
+ * data-consistency system is (A_S^H A_S + I/tau) x = A_S^H A_S x^t - d^t + v/tau.  CS_RECON_SKETCH_LEARNED runs
  * Algorithm 1 with each subproblem's FISTA started at
  * z0 = x^t + s_o CNN(x^t / s_x, d^t / s_d) (s_d = rms(d^t), s_o = alpha s_d,
  * s_x = rms(x^t) or s_o while x^t = 0) when the FP64 subproblem objective

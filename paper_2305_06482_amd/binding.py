@@ -26,7 +26,7 @@ CS_NONCART = 1
 CS_RECON_FULL = 0
 CS_RECON_SKETCH = 1
 CS_RECON_SKETCH_LEARNED = 2
-CS_REG_L1WAV, CS_REG_L2 = 0, 1
+CS_REG_L1WAV, CS_REG_L2, CS_REG_TV = 0, 1, 2
 CS_SKETCH_RADEMACHER, CS_SKETCH_GAUSSIAN = 0, 1
 
 EXPORTED = [
@@ -81,6 +81,7 @@ class ReconParams(ctypes.Structure):
         ("x_ref", ctypes.c_void_p),
         ("cnn", ctypes.c_void_p),
         ("reg", ctypes.c_int),
+        ("n_cg", ctypes.c_int),
     ]
 
 
@@ -361,9 +362,10 @@ class Context:
 
     def recon_run(self, y, mode="sketch", lam=1e-3, T=10, K=5, V=2, S=2, seed=0, t0=1,
                   step=0.0, n_pow=30, reuse_b=False, x=None, x_ref=None, cnn=None,
-                  reg="l1wav"):
+                  reg="l1wav", n_cg=5):
         """Algorithm 1 (mode "sketch", "learned") or the plain solver ("full")
-        with regularizer reg: "l1wav" (FISTA) or "l2" (conjugate gradients)."""
+        with regularizer reg: "l1wav" (FISTA), "l2" (conjugate gradients) or
+        "tv" (PDHG with n_cg CG iterations per data-consistency step)."""
         self._data(y, self.C)
         if x is None:
             x = torch.zeros(self.shape, dtype=torch.complex64, device=self.device)
@@ -374,7 +376,8 @@ class Context:
         p.mode = {"sketch": CS_RECON_SKETCH, "full": CS_RECON_FULL,
                   "learned": CS_RECON_SKETCH_LEARNED}[mode]
         p.cnn = None if cnn is None else cnn._n.value
-        p.reg = {"l1wav": CS_REG_L1WAV, "l2": CS_REG_L2}[reg]
+        p.reg = {"l1wav": CS_REG_L1WAV, "l2": CS_REG_L2, "tv": CS_REG_TV}[reg]
+        p.n_cg = int(n_cg)
         p.lam = float(lam)
         p.T, p.K, p.V, p.S = int(T), int(K), int(V), int(S)
         p.seed = int(seed)

@@ -441,7 +441,7 @@ int create_impl(const cs_geom* g, void* stream, cs_ctx** out) {
     g_create_error = "allocation failed";
     return rc;
   }
-  for (int i = 0; i < 10; ++i) {
+  for (int i = 0; i < 12; ++i) {
     float2* p = nullptr;
     if ((rc = alloc((void**)&p, f2 * c->D))) {
       cs_destroy(c);
@@ -449,6 +449,11 @@ int create_impl(const cs_geom* g, void* stream, cs_ctx** out) {
       return rc;
     }
     c->img.push_back(p);
+  }
+  if ((rc = alloc((void**)&c->tvu, f2 * c->D * c->ndim))) {
+    cs_destroy(c);
+    g_create_error = "allocation failed";
+    return rc;
   }
   if (hipHostMalloc((void**)&c->host_red, sizeof(double) * 2 * 1024) != hipSuccess) {
     cs_destroy(c);
@@ -678,6 +683,7 @@ void cs_destroy(cs_ctx* c) {
   for (int a = 0; a < 3; ++a) fr(c->da[a]);
   fr(c->dp_z); fr(c->dp_y); fr(c->da_y1d);
   for (auto* p : c->img) fr(p);
+  fr(c->tvu);
   for (auto& kv : c->plans) fr(kv.second.tw);
   if (c->host_red) (void)hipHostFree(c->host_red);
   for (auto& r : c->prof_recs) {
@@ -907,9 +913,12 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
     return fail(c, CS_EINVAL, "recon mode");
   const bool learned = p->mode == CS_RECON_SKETCH_LEARNED;
   if (learned && !p->cnn) return fail(c, CS_EINVAL, "learned mode needs a network");
-  if (p->reg != CS_REG_L1WAV && p->reg != CS_REG_L2) return fail(c, CS_EINVAL, "regularizer");
+  if (p->reg != CS_REG_L1WAV && p->reg != CS_REG_L2 && p->reg != CS_REG_TV)
+    return fail(c, CS_EINVAL, "regularizer");
   const bool l2 = p->reg == CS_REG_L2;
-  if (l2 && learned) return fail(c, CS_EINVAL, "the learned warm start is for l1-wavelet only");
+  const bool tvr = p->reg == CS_REG_TV;
+  if ((l2 || tvr) && learned)
+    return fail(c, CS_EINVAL, "the learned warm start is for l1-wavelet only");
   if (p->T < 0 || (p->mode != CS_RECON_FULL && p->K < 1))
     return fail(c, CS_EINVAL, "iteration counts");
   if (st) st->n_warm_accepted = st->n_warm_rejected = 0;
@@ -943,16 +952,16 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
   const int n_pow = p->n_pow > 0 ? p->n_pow : 30;
   long long nfull = 0, nsk = 0, nprox = 0;
   double alpha = p->step;
-  if (l2) alpha = 0.0;  // CG needs no step size
+  if (l2 || tvr) alpha = 0.0;  // CG and PDHG need no FISTA step
   if (p->mode != CS_RECON_FULL) {
     CS_TRY(sketch_impl(c, y, p->V, p->S, p->seed, p->t0, 0, c->smaps, nullptr));
-    if (alpha <= 0 && !l2) {
+    if (alpha <= 0 && !l2 && !tvr) {
       double L = 0;
       CS_TRY(power_iter(c, c->smaps, Ch, n_pow, &L));
       nsk += n_pow + 1;
       alpha = 1.0 / L;
     }
-  } else if (alpha <= 0 && !l2) {
+  } else if (alpha <= 0 && !l2 && !tvr) {
     double L = 0;
     CS_TRY(power_iter(c, c->maps, C, n_pow, &L));
     nfull += n_pow + 1;
@@ -1013,7 +1022,62 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
     CS_HIP(c, hipEventRecord(evd[it], c->stream));
     return CS_OK;
   };
-  if (l2 && p->mode == CS_RECON_FULL) {
+  if (tvr) {
+    // PDHG on G + lam ||T x||_1 (theta = 1, tau = sigma = 1/sqrt(4 ndim));
+    // G's prox is the CG solve of (N + I/tau) x = rhs0 + v/tau, with N and
+    // rhs0 = b (plain problem) or N_S and N_S x^t - d (subproblem)
+    const double step = 1.0 / std::sqrt(4.0 * c->ndim);
+    const float tau = (float)step, sigma = (float)step, itau = (float)(1.0 / step);
+    const int n_cg = p->n_cg > 0 ? p->n_cg : 5;
+    float2* pd = c->img[2];
+    float2* xbar = c->img[3];
+    float2* xold = c->img[4];
+    float2* q = c->img[5];
+    float2* r = c->img[6];
+    float2* v = c->img[7];
+    float2* rhs0 = c->img[10];
+    float2* xt = c->img[11];
+    auto pdhg = [&](const float2* maps, int ncoil, int K, int kind, long long* napp,
+                    int rec_base) -> int {
+      CS_TRY(vec_fill(c, c->tvu, D * c->ndim, 0.f, 0.f));
+      CS_TRY(vec_copy(c, xbar, x, D));
+      for (int k = 0; k < K; ++k) {
+        CS_TRY(tv_dual_step(c, c->tvu, xbar, sigma, p->lam));
+        CS_TRY(tv_primal_step(c, v, x, c->tvu, tau));
+        CS_TRY(vec_copy(c, xold, x, D));
+        CS_TRY(vec_axpby(c, r, 1.f, rhs0, itau, v, D));
+        long long n = 0;
+        CS_TRY(cg_solve(c, maps, ncoil, itau, x, false, r, pd, q, n_cg, kind, &timed_fn, &n));
+        *napp += n;
+        CS_TRY(vec_axpby(c, xbar, 2.f, x, -1.f, xold, D));
+        if (rec_base >= 0) CS_TRY(record(rec_base + k));
+      }
+      return CS_OK;
+    };
+    if (p->mode == CS_RECON_FULL) {
+      CS_TRY(vec_copy(c, rhs0, b, D));
+      CS_TRY(pdhg(c->maps, C, p->T, 0, &nfull, 0));
+    } else {
+      for (int it = 0; it < p->T; ++it) {
+        const int t = p->t0 + it;
+        CS_TRY(timed(0, [&] { return op_normal(c, c->maps, C, x, g); }));
+        ++nfull;
+        CS_TRY(vec_axpby(c, d, 1.f, g, -1.f, b, D));
+        if (it > 0)
+          CS_TRY(timed(3, [&] {
+            return sketch_impl(c, y, p->V, p->S, p->seed, t, 0, c->smaps, nullptr);
+          }));
+        CS_TRY(vec_copy(c, xt, x, D));
+        CS_TRY(timed(1, [&] { return op_normal(c, c->smaps, Ch, xt, rhs0); }));
+        ++nsk;
+        CS_TRY(vec_axpby(c, rhs0, 1.f, rhs0, -1.f, d, D));
+        long long n = 0;
+        CS_TRY(pdhg(c->smaps, Ch, p->K, 1, &n, -1));
+        nsk += n;
+        CS_TRY(record(it));
+      }
+    }
+  } else if (l2 && p->mode == CS_RECON_FULL) {
     // CG on (A^H A + lam I) x = b, one iteration per record
     float2* r = c->img[6];
     float2* pd = c->img[2];

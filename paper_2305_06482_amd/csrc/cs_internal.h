@@ -125,6 +125,7 @@ struct cs_ctx {
   double* red = nullptr;          // reduction partials
   double* red_out = nullptr;      // final reduction values (device)
   double* host_red = nullptr;     // pinned host copy
+  float2* tvu = nullptr;          // [ndim][D] PDHG dual variable of the TV term
 
   // sketch cache
   bool have_U = false;
@@ -248,6 +249,10 @@ int sketch_impl(cs_ctx* c, const float2* y, int V, int S, uint64_t seed, int t, 
 int inner_fista(cs_ctx* c, float2* x, int Ch, int K, float a, float tau_l,
                 const std::function<int(int, const std::function<int()>&)>* timed,
                 const float2* start);
+// PDHG updates of the l1-TV regularizer: u <- clip(u + sigma T xbar, lam)
+// (u holds ndim components of D), v = x - tau T^H u
+int tv_dual_step(cs_ctx* c, float2* u, const float2* xbar, float sigma, float lam);
+int tv_primal_step(cs_ctx* c, float2* v, const float2* x, const float2* u, float tau);
 // K CG iterations on (A^H A + lam I) u = rhs (r holds rhs on entry)
 int cg_solve(cs_ctx* c, const float2* maps, int ncoil, float lam, float2* u, bool u_zero,
              float2* r, float2* p, float2* q, int K, int kind,
