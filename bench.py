@@ -354,6 +354,58 @@ def gfactor_bench(args, log, n=256, C=8, accel=3, trials=60, lam=1e-2, sigma=1e-
     return res
 
 
+def tv_tta(args, log, lam=5e-3, n_cg=3, ref_iters=3000, full_iters=400,
+           runs=((20, 60, 11, 1), (50, 24, 11, 1), (20, 60, 6, 6)), seed=3000):
+    """l1-TV (Sec. 3.3.2) time to accuracy on the 48^3 cones instance
+    (32 coils): PDHG with n_cg CG iterations per data-consistency step,
+    full-coil against Algorithm 1 with K PDHG iterations per subproblem.
+    x_inf = ref_iters full-coil PDHG iterations.  Times are GPU event times
+    plus set-up."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2305_06482_amd import Context
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    p = synth.make_cones_small(seed_base=seed)
+    ctx = Context(p.shape, p.n_coils, "noncart", nsamp=p.coords.shape[0], wav_levels=3)
+    maps = torch.from_numpy(p.maps).to(torch.complex64).to(dev)
+    w = torch.from_numpy(p.dcf).to(torch.float32).to(dev)
+    ctx.set_operator(maps, coords=torch.from_numpy(p.coords).to(torch.float32).to(dev), dcf=w)
+    y = ctx.sense_apply(maps, torch.from_numpy(p.x_true).to(torch.complex64).to(dev))
+    y += torch.from_numpy(p.noise).to(torch.complex64).to(dev) * w.sqrt()[:, None].to(torch.complex64)
+    x_inf = ctx.recon_run(y, mode="full", reg="tv", lam=lam, T=ref_iters, n_cg=n_cg).x
+
+    def times(r):
+        out = {"final_dist": r.dist[-1], "prep_ms": r.prep_ms,
+               "full_applies": r.n_full_applies, "sketched_applies": r.n_sketch_applies}
+        for thr in TTA_THRESHOLDS:
+            i = first_below(r.dist, thr)
+            out[f"{thr:g}"] = None if i is None else {
+                "iterations": i + 1, "total_ms": r.time_ms[i] + r.prep_ms}
+        return out
+
+    res = {"shape": list(p.shape), "coils": p.n_coils, "lam": lam, "n_cg": n_cg,
+           "x_inf_iterations": ref_iters}
+    rf = ctx.recon_run(y, mode="full", reg="tv", lam=lam, T=full_iters, n_cg=n_cg, x_ref=x_inf)
+    res["full_coil"] = times(rf)
+    for K, T, V, S in runs:
+        r = ctx.recon_run(y, mode="sketch", reg="tv", lam=lam, T=T, K=K, V=V, S=S, seed=p.seed,
+                          n_cg=n_cg, x_ref=x_inf)
+        e = times(r)
+        e["speedup_total"] = {k: res["full_coil"][k]["total_ms"] / e[k]["total_ms"]
+                              for k in (f"{t:g}" for t in TTA_THRESHOLDS)
+                              if res["full_coil"].get(k) and e.get(k)}
+        res[f"sketched_K{K}_V{V}S{S}"] = e
+    ctx.close()
+    res["wall_s"] = round(time.time() - t0, 1)
+    log("l1-TV time to accuracy (48^3 cones): " + "; ".join(
+        f"{k}: " + ", ".join(f"{t}: {v[t] and round(v[t]['total_ms'], 1)} ms"
+                            for t in (f"{x:g}" for x in TTA_THRESHOLDS))
+        for k, v in res.items() if isinstance(v, dict) and "final_dist" in v))
+    return res
+
+
 def design_ablation(args, log, n=256, C=8, seeds=20, chats=(3, 4), T=10, K=10, lam=1e-3,
                     T_base=300, seed_base=8100):
     """Sketching-matrix design (Sec. 3.2.1) on a synthetic 2D radial slice
@@ -532,6 +584,8 @@ def main():
     ap.add_argument("--small", action="store_true", help="48^3 instance (quick check)")
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-accuracy runs")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-slice batch")
+    ap.add_argument("--no-tv", action="store_true",
+                    help="skip the l1-TV time-to-accuracy runs (48^3 cones)")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the sketching-matrix design ablation (2D radial)")
     ap.add_argument("--no-gfactor", action="store_true",
@@ -696,6 +750,8 @@ def main():
     out["precision"] = precision_report(ctx, p, Ch, cpu_ref, log)
     if not args.no_batched and not args.small:
         out["batched_radial"] = batched_bench(args, log)
+    if not args.no_tv and not args.small:
+        out["tv_time_to_accuracy"] = tv_tta(args, log)
     if not args.no_ablation and not args.small:
         out["sketch_design_ablation"] = design_ablation(args, log)
     if not args.no_gfactor and not args.small:
