@@ -18,8 +18,10 @@ Readings:
   * FISTA momentum restarts (tau = 1, z = x^t) at every subproblem.
   * The power iteration starts from the normalised all-ones image, runs 30
     normalised applies and reports L = ||N v_30||.
-  * Alg. 1's initial compression keeps all C coils and the optional
-    classical-sketch initialisation is off; x^0 = 0.
+  * Alg. 1's initial compression keeps all C coils; x^0 = 0.  The optional
+    classical-sketch initialisation (off by default) uses the structured
+    sketch drawn at t = 0 on both the model and the data and the same FISTA
+    (step from the first subproblem) for a given number of iterations.
   * K inner FISTA iterations per subproblem.
 """
 from __future__ import annotations
@@ -97,12 +99,28 @@ class SketchState:
         return sk.sketch_for_iteration(self.vmaps, V, S, seed, t, dist)[0]
 
 
+def classical_init(st, normal_maps_fn, adjoint_maps_fn, y, x0, V, S, seed, K0, lam, alpha,
+                   levels=4, dist="rademacher"):
+    """Alg. 1's optional initialisation: x^1 = argmin 1/2 ||S^0 A x - S^0 y||^2
+    + g(x), with S^0 the structured sketch drawn at t = 0 applied to the
+    model (sketched maps) and to the data (y -> S~^0 U^H y per sample), by
+    K0 FISTA iterations from x0.  ``adjoint_maps_fn(y, maps)`` applies A^H."""
+    C = st.vmaps.shape[-1]
+    m0, entries = sk.sketch_for_iteration(st.vmaps, V, S, seed, 0, dist)
+    St = sk.sketch_matrix(V, S, C, entries)
+    ys = sk.virtual_data(y, st.U) @ St.T
+    bs = adjoint_maps_fn(ys, m0)
+    return fista_full(lambda v: normal_maps_fn(v, m0), bs, x0, alpha, lam, K0, levels)
+
+
 def coil_sketch(normal_maps_fn, maps, y, dcf, b, x0, V, S, seed, T, K, lam,
-                alpha=None, levels=4, n_pow=30, callback=None, t0=1, dist="rademacher"):
+                alpha=None, levels=4, n_pow=30, callback=None, t0=1, dist="rademacher",
+                init_iters=0, adjoint_maps_fn=None):
     """Algorithm 1 with FISTA inner solves.
 
     ``normal_maps_fn(x, maps)`` applies A^H A built on the given maps.
-    ``b`` = A^H y.  Returns (x^T, alpha, state).
+    ``b`` = A^H y.  With init_iters > 0, x^1 comes from the classical-sketch
+    initialisation (``adjoint_maps_fn`` needed).  Returns (x^T, alpha, state).
     """
     st = SketchState(maps, y, dcf)
     if alpha is None:
@@ -110,6 +128,9 @@ def coil_sketch(normal_maps_fn, maps, y, dcf, b, x0, V, S, seed, T, K, lam,
         L = power_iteration(lambda v: normal_maps_fn(v, m1), x0.shape, n_pow)
         alpha = 1.0 / L
     x = np.array(x0, dtype=np.complex128, copy=True)
+    if init_iters > 0:
+        x = classical_init(st, normal_maps_fn, adjoint_maps_fn, y, x, V, S, seed, init_iters,
+                           lam, alpha, levels, dist)
     for t in range(t0, t0 + T):
         d = normal_maps_fn(x, maps) - b
         mt = st.maps_for(V, S, seed, t, dist)

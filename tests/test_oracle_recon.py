@@ -124,3 +124,38 @@ def test_objective_decreases_and_nrmse():
                      1.0, 1e-3, 30, callback=lambda i, xi: objs.append(recon.objective(xi, fwd, y, 1e-3)))
     assert objs[-1] < objs[0]
     assert recon.nrmse(x, x) == 0.0
+
+
+def test_classical_init_with_all_coils_is_plain_fista():
+    # V = C, S = 0: S^0 = U^H is unitary on the coils, so the sketched problem
+    # is the full problem and the initialisation is plain FISTA
+    shape, x, maps, mask, y = _small(seed=40, n=16, C=6)
+    C = maps.shape[-1]
+    nf = lambda v, m: cart.normal(v, m, mask)
+    af = lambda yy, m: cart.adjoint(yy.reshape(shape + (m.shape[-1],)), m, mask)
+    b = cart.adjoint(y.reshape(shape + (C,)), maps, mask)
+    st = recon.SketchState(maps, y, None)
+    alpha = 1.0 / recon.power_iteration(lambda v: nf(v, maps), shape)
+    lam = 1e-3
+    x1 = recon.classical_init(st, nf, af, y, np.zeros(shape, complex), C, 0, 3, 15, lam, alpha,
+                              levels=2)
+    ref = recon.fista_full(lambda v: nf(v, maps), b, np.zeros(shape, complex), alpha, lam, 15,
+                           levels=2)
+    assert np.linalg.norm(x1 - ref) < 1e-10 * np.linalg.norm(ref)
+
+
+def test_classical_init_lowers_the_sketched_objective():
+    # the initialisation minimises 1/2 ||S^0 A x - S^0 y||^2 + lam ||Psi x||_1
+    shape, x, maps, mask, y = _small(seed=41, n=16, C=6)
+    C, V, S, seed, lam = maps.shape[-1], 2, 2, 5, 1e-3
+    nf = lambda v, m: cart.normal(v, m, mask)
+    af = lambda yy, m: cart.adjoint(yy.reshape(shape + (m.shape[-1],)), m, mask)
+    st = recon.SketchState(maps, y, None)
+    m0, ent = sk.sketch_for_iteration(st.vmaps, V, S, seed, 0)
+    ys = sk.virtual_data(y, st.U) @ sk.sketch_matrix(V, S, C, ent).T
+    fwd = lambda v: cart.forward(v, m0, mask).reshape(-1, V + S)
+    alpha = 1.0 / recon.power_iteration(lambda v: nf(v, m0), shape)
+    obj = lambda v: 0.5 * np.linalg.norm(fwd(v) - ys) ** 2 + lam * recon.wv.l1_norm(v, 2)
+    x1 = recon.classical_init(st, nf, af, y, np.zeros(shape, complex), V, S, seed, 40, lam,
+                              alpha, levels=2)
+    assert obj(x1) < 0.2 * obj(np.zeros(shape, complex))
