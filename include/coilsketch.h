@@ -162,6 +162,12 @@ typedef struct {
                         CS_REG_TV (PDHG); l2 and TV: FULL and SKETCH modes only */
   int n_cg;          /* CS_REG_TV: CG iterations per PDHG data-consistency step
                         (<= 0 selects 5) */
+  int init_iters;    /* SKETCH / SKETCH_LEARNED with l1-wavelet: > 0 runs Alg. 1's
+                        classical-sketch initialisation, x^1 = argmin
+                        1/2 ||S^0 A x - S^0 y||^2 + g(x) with the sketch of
+                        t = 0 on maps and data (S~^0 U^H y per sample), by this
+                        many FISTA iterations from x^{t0}; the sketched data
+                        buffer ([N][V+S]) is allocated on its first use */
 } cs_recon_params;
 
 typedef struct {

@@ -684,6 +684,7 @@ void cs_destroy(cs_ctx* c) {
   fr(c->dp_z); fr(c->dp_y); fr(c->da_y1d);
   for (auto* p : c->img) fr(p);
   fr(c->tvu);
+  fr(c->ysk);
   for (auto& kv : c->plans) fr(kv.second.tw);
   if (c->host_red) (void)hipHostFree(c->host_red);
   for (auto& r : c->prof_recs) {
@@ -919,6 +920,9 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
   const bool tvr = p->reg == CS_REG_TV;
   if ((l2 || tvr) && learned)
     return fail(c, CS_EINVAL, "the learned warm start is for l1-wavelet only");
+  if (p->init_iters < 0 ||
+      (p->init_iters > 0 && (l2 || tvr || p->mode == CS_RECON_FULL)))
+    return fail(c, CS_EINVAL, "the classical-sketch initialisation is for l1-wavelet Algorithm 1");
   if (p->T < 0 || (p->mode != CS_RECON_FULL && p->K < 1))
     return fail(c, CS_EINVAL, "iteration counts");
   if (st) st->n_warm_accepted = st->n_warm_rejected = 0;
@@ -969,6 +973,69 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
   }
   const float a = (float)alpha;
   const float tau_l = (float)(alpha * p->lam);
+  if (p->init_iters > 0) {
+    // Alg. 1's initialisation: x^1 = argmin 1/2 ||S^0 A x - S^0 y||^2 + g(x)
+    // with the structured sketch of t = 0 on the maps and on the data,
+    // by plain FISTA with the first subproblem's step
+    const int V = p->V, S = p->S, cols = C - p->V;
+    std::vector<double> R((size_t)S * std::max(cols, 0), 0.0);
+    if (S > 0) {
+      if (c->sketch_dist == CS_SKETCH_GAUSSIAN) {
+        gaussian(p->seed, 0, S, cols, R);
+      } else {
+        std::vector<int8_t> sg;
+        rademacher(p->seed, 0, S, cols, sg);
+        for (size_t k = 0; k < sg.size(); ++k) R[k] = sg[k];
+      }
+    }
+    // M[j][c] = (S~^0 U^H)[j][c]: rows j < V select virtual coil j, rows
+    // V + i combine the virtual coils V.. with R[i][.] / sqrt(S)
+    std::vector<double> M((size_t)2 * Ch * C, 0.0);
+    const double rs = S > 0 ? 1.0 / std::sqrt((double)S) : 0.0;
+    for (int cc = 0; cc < C; ++cc) {
+      for (int j = 0; j < V; ++j) {
+        M[2 * (j * C + cc)] = c->U[2 * (cc * C + j)];
+        M[2 * (j * C + cc) + 1] = -c->U[2 * (cc * C + j) + 1];
+      }
+      for (int i = 0; i < S; ++i)
+        for (int bb = 0; bb < cols; ++bb) {
+          const double w = R[(size_t)i * cols + bb] * rs;
+          M[2 * ((V + i) * C + cc)] += w * c->U[2 * (cc * C + V + bb)];
+          M[2 * ((V + i) * C + cc) + 1] -= w * c->U[2 * (cc * C + V + bb) + 1];
+        }
+    }
+    const size_t need = (size_t)std::max(1LL, c->N) * Ch;
+    if (need > c->ysk_elems) {
+      if (c->ysk) CS_HIP(c, hipFree(c->ysk));
+      c->ysk = nullptr;
+      c->ysk_elems = 0;
+      CS_HIP(c, hipMalloc(&c->ysk, sizeof(float2) * need));
+      c->ysk_elems = need;
+    }
+    CS_TRY(coil_mix_rows(c, c->N, y, C, 0, C, M.data(), Ch, c->ysk, Ch, 0, 1.0f));
+    CS_TRY(sketch_impl(c, y, p->V, p->S, p->seed, 0, 0, c->smaps, nullptr));
+    float2* bs = c->img[10];
+    CS_TRY(chunk_loop(c, Ch, op_adjoint, c->smaps, c->ysk, bs));
+    float2* z0 = c->img[2];
+    float2* g0 = c->img[5];
+    float2* v0 = c->img[6];
+    float2* x0n = c->img[7];
+    CS_TRY(vec_copy(c, z0, x, D));
+    double tau = 1.0;
+    for (int k = 0; k < p->init_iters; ++k) {
+      CS_TRY(op_normal(c, c->smaps, Ch, z0, g0));
+      ++nsk;
+      CS_TRY(vec_fista_step(c, v0, z0, a, g0, -1.f, bs, D));
+      CS_TRY(prox_l1(c, v0, tau_l, x0n));
+      ++nprox;
+      const double tn = (1.0 + std::sqrt(1.0 + 4.0 * tau * tau)) / 2.0;
+      const float beta = (float)((tau - 1.0) / tn);
+      tau = tn;
+      CS_TRY(vec_momentum(c, z0, x, x0n, beta, D));
+    }
+    // the loop's first subproblem uses the sketch of t0 again
+    CS_TRY(sketch_impl(c, y, p->V, p->S, p->seed, p->t0, 0, c->smaps, nullptr));
+  }
   // per-call events, destroyed on every return path
   struct Events {
     std::vector<hipEvent_t> all;

@@ -126,6 +126,8 @@ struct cs_ctx {
   double* red_out = nullptr;      // final reduction values (device)
   double* host_red = nullptr;     // pinned host copy
   float2* tvu = nullptr;          // [ndim][D] PDHG dual variable of the TV term
+  float2* ysk = nullptr;          // [N][C^] sketched data of the classical initialisation
+  size_t ysk_elems = 0;           // (allocated on its first use)
 
   // sketch cache
   bool have_U = false;
@@ -238,6 +240,10 @@ int covariance_eig(cs_ctx* c, const float2* y);
 int coil_mix(cs_ctx* c, const float2* in, int in_ldc, int in_c0, int cin,
              const double* M, int cout, float2* out, int out_ldc, int out_c0,
              float out_scale);
+// the same over `rows` rows (data [N][.] instead of maps [D][.])
+int coil_mix_rows(cs_ctx* c, long long rows, const float2* in, int in_ldc, int in_c0, int cin,
+                  const double* M, int cout, float2* out, int out_ldc, int out_c0,
+                  float out_scale);
 
 // operators and solver pieces (api.hip)
 int op_normal(cs_ctx* c, const float2* maps, int ncoil, const float2* x,

@@ -356,6 +356,13 @@ int covariance_eig(cs_ctx* c, const float2* y) {
 
 int coil_mix(cs_ctx* c, const float2* in, int in_ldc, int in_c0, int cin, const double* M,
              int cout, float2* out, int out_ldc, int out_c0, float out_scale) {
+  return coil_mix_rows(c, c->D, in, in_ldc, in_c0, cin, M, cout, out, out_ldc, out_c0,
+                       out_scale);
+}
+
+int coil_mix_rows(cs_ctx* c, long long rows, const float2* in, int in_ldc, int in_c0, int cin,
+                  const double* M, int cout, float2* out, int out_ldc, int out_c0,
+                  float out_scale) {
   if (cin < 1 || cout < 1 || cin > kMaxC || cout > 64)
     return fail(c, CS_EINVAL, "coil_mix sizes");
   const int K = 2 * cin, N2 = 2 * cout;
@@ -417,10 +424,11 @@ int coil_mix(cs_ctx* c, const float2* in, int in_ldc, int in_c0, int cin, const 
   std::memcpy(c->stage[k], frag.data(), bytes);
   CS_HIP(c, hipMemcpyAsync(c->mixB, c->stage[k], bytes, hipMemcpyHostToDevice, c->stream));
   CS_HIP(c, hipEventRecord(c->stage_ev[k], c->stream));
-  const long long tiles = (c->D + 15) / 16;
+  if (rows <= 0) return CS_OK;
+  const long long tiles = (rows + 15) / 16;
   const unsigned nb = (unsigned)((tiles + 3) / 4);
   CS_KLAUNCH(c, K_MIX, k_coil_mix, dim3(nb), dim3(256), 0, c->stream, in, in_ldc, in_c0, cin,
-                     c->D, (const v4s*)c->mixB, nB, nK, nN, out, out_ldc, out_c0, cout,
+                     rows, (const v4s*)c->mixB, nB, nK, nN, out, out_ldc, out_c0, cout,
                      out_scale);
   CS_HIP(c, hipGetLastError());
   return CS_OK;

@@ -122,3 +122,52 @@ def test_s0_diverges_where_s1_converges_on_gpu():
         else:
             assert d[-1] < 1e-3, d
     ctx.close()
+
+
+@pytest.mark.parametrize("kind", ["cart", "radial"])
+def test_classical_init_matches_oracle(kind):
+    """Alg. 1 with the classical-sketch initialisation (sketched data
+    S~^0 U^H y, mixed on MFMA over the N data rows) against the oracle."""
+    dev()
+    import torch
+    from paper_2305_06482_amd import Context
+    from oracle import nufft
+    case(f"classical-sketch initialisation, {kind}")
+    T, K, K0 = 3, 5, 10
+    if kind == "cart":
+        p = synth.make_cart_small()
+        C = p.n_coils
+        y = cart.forward(p.x_true, p.maps, p.mask) + p.noise.reshape(p.shape + (C,)) * \
+            p.mask[..., None]
+        y = y.astype(np.complex64).astype(np.complex128)
+        maps = p.maps.astype(np.complex64).astype(np.complex128)
+        nf = lambda v, m: cart.normal(v, m, p.mask)
+        af = lambda yy, m: cart.adjoint(yy.reshape(p.shape + (m.shape[-1],)), m, p.mask)
+        b = cart.adjoint(y, maps, p.mask)
+        ctx = Context(p.shape, C, "cart")
+        ctx.set_operator(t(maps), mask=t(p.mask, torch.uint8))
+        y2, dcf, yt = y.reshape(-1, C), None, t(y)
+    else:  # N = 6144 samples on a 64 x 64 image: rows != pixels
+        p = synth.make_radial(64, 48, 8, 2, 2, seed_base=7400)
+        C = p.n_coils
+        c32, w32 = p.coords.astype(np.float32), p.dcf.astype(np.float32)
+        maps = p.maps.astype(np.complex64).astype(np.complex128)
+        plan = nufft.Plan(p.shape, c32.astype(np.float64), w32.astype(np.float64))
+        y2 = (plan.forward(p.x_true, maps) + p.noise * np.sqrt(w32)[:, None]
+              ).astype(np.complex64).astype(np.complex128)
+        nf = lambda v, m: plan.normal(v, m)
+        af = lambda yy, m: plan.adjoint(yy, m)
+        b = plan.adjoint(y2, maps)
+        dcf = w32.astype(np.float64)
+        ctx = Context(p.shape, C, "noncart", nsamp=c32.shape[0], wav_levels=4)
+        ctx.set_operator(t(maps.astype(np.complex64)), coords=t(c32), dcf=t(w32))
+        yt = t(y2)
+    xr, alpha, _ = orecon.coil_sketch(nf, maps, y2, dcf, b, np.zeros(p.shape, complex), p.V,
+                                      p.S, p.seed, T, K, p.lam, init_iters=K0,
+                                      adjoint_maps_fn=af)
+    res = ctx.recon_run(yt, mode="sketch", lam=p.lam, T=T, K=K, V=p.V, S=p.S, seed=p.seed,
+                        step=alpha, init_iters=K0)
+    e = orecon.nrmse(h(res.x), xr)
+    assert e < 1e-3, e
+    assert res.n_sketch_applies == K0 + T * K
+    ctx.close()
