@@ -91,6 +91,30 @@ def first_below(dist, thr):
     return None
 
 
+def image_quality(x, ref, sigma=1.5):
+    """NRMSE, SSIM and HFEN of the magnitude image |x| against |ref| (the
+    metrics of Sec. 3.2.1 / 3.3.1, computed against the synthetic phantom).
+    SSIM (Wang et al. 2004): Gaussian window of width sigma, K1 = 0.01,
+    K2 = 0.03, dynamic range max |ref|, averaged over the image.  HFEN
+    (Ravishankar and Bresler 2011): relative l2 error of the
+    Laplacian-of-Gaussian (width sigma) filtered images."""
+    import numpy as np
+    from scipy import ndimage
+    a = np.abs(np.asarray(x, dtype=np.complex128))
+    r = np.abs(np.asarray(ref, dtype=np.complex128))
+    L = r.max()
+    c1, c2 = (0.01 * L) ** 2, (0.03 * L) ** 2
+    g = lambda v: ndimage.gaussian_filter(v, sigma, mode="wrap")
+    ma, mr = g(a), g(r)
+    va, vr, cov = g(a * a) - ma * ma, g(r * r) - mr * mr, g(a * r) - ma * mr
+    ssim = ((2 * ma * mr + c1) * (2 * cov + c2)) / ((ma * ma + mr * mr + c1) * (va + vr + c2))
+    la = ndimage.gaussian_laplace(a, sigma, mode="wrap")
+    lr = ndimage.gaussian_laplace(r, sigma, mode="wrap")
+    return {"nrmse": float(np.linalg.norm(a - r) / np.linalg.norm(r)),
+            "ssim": float(np.mean(ssim)),
+            "hfen": float(np.linalg.norm(la - lr) / np.linalg.norm(lr))}
+
+
 def time_to_accuracy(ctx, y, p, args, log, ref_iters, full_iters, outer_iters, chunk,
                      cnn=None, lam=None, restart=0):
     """Time to d(x^t) = ||x^t - x_inf|| / ||x_inf|| <= thr (Sec. 3.3.1) for the
@@ -147,6 +171,7 @@ def time_to_accuracy(ctx, y, p, args, log, ref_iters, full_iters, outer_iters, c
     rf = ctx.recon_run(y, mode="full", lam=lam, T=full_iters, step=0.0, n_pow=30,
                        reuse_b=False, x=x, x_ref=x_inf)
     full = summarize(rf, 1, 0, 31, 0)
+    full["image_quality"] = image_quality(rf.x.cpu().numpy(), p.x_true)
     log(f"{p.name} full-coil FISTA: final d {full['final_dist']:.3e}, "
         + ", ".join(f"{k}: {v and round(v['total_ms'], 1)} ms" for k, v in full.items()
                     if k in {f'{t:g}' for t in TTA_THRESHOLDS}))
@@ -211,6 +236,7 @@ def time_to_accuracy(ctx, y, p, args, log, ref_iters, full_iters, outer_iters, c
             sk[f"speedup_vs_{name}"] = {f"{t:g}": fr[f"{t:g}"]["total_ms"] / sk[f"{t:g}"]["total_ms"]
                                         for t in TTA_THRESHOLDS
                                         if fr.get(f"{t:g}") and sk.get(f"{t:g}")}
+        sk["image_quality"] = image_quality(rs.x.cpu().numpy(), p.x_true)
         res[f"{label}_K{K}" + ("" if (rV, rS) == (V, S) else f"_V{rV}S{rS}")] = sk
     return res
 
@@ -626,6 +652,8 @@ def main():
     def dt(a, dtype):
         return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).to(dev)
 
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
     ctx = Context(p.shape, C, "noncart", nsamp=p.coords.shape[0], sigma=1.25, wav_levels=4)
     maps = dt(p.maps, torch.complex64)
     coords = dt(p.coords, torch.float32)
@@ -633,6 +661,11 @@ def main():
     t0 = time.time()
     ctx.set_operator(maps, coords=coords, dcf=dcf)
     log(f"operator set (trajectory sorted and binned) in {time.time() - t0:.1f} s")
+    torch.cuda.synchronize()
+    # device memory held by the context and its inputs (the library allocates
+    # with hipMalloc, outside torch's pool): every coil stays resident
+    mem = {"context_and_inputs_bytes": int(free0 - torch.cuda.mem_get_info()[0]),
+           "maps_bytes": int(maps.numel() * 8), "total_bytes": int(torch.cuda.mem_get_info()[1])}
     x_true = dt(p.x_true, torch.complex64)
     y = ctx.sense_apply(maps, x_true)
     y += dt(p.noise, torch.complex64) * torch.sqrt(dcf)[:, None].to(torch.complex64)
@@ -740,6 +773,7 @@ def main():
                               "sketched_normal": ms_sk / args.steps,
                               "prox": ms_prox / args.steps, "sketch": ms_sketch / args.steps},
         "model_bytes": {"sketched": b_sk, "full": b_full},
+        "device_memory": mem,
         "kernels": kern,
         "roofline": roof,
     }
