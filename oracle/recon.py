@@ -18,7 +18,9 @@ Readings:
   * FISTA momentum restarts (tau = 1, z = x^t) at every subproblem.
   * The power iteration starts from the normalised all-ones image, runs 30
     normalised applies and reports L = ||N v_30||.
-  * Alg. 1's initial compression keeps all C coils; x^0 = 0.  The optional
+  * Alg. 1's initial compression keeps all C coils unless C0 < C is asked
+    for (``coil_sketch_compressed``): then the model and the data are rotated
+    onto the PCA virtual coils and truncated to the first C0; x^0 = 0.  The optional
     classical-sketch initialisation (off by default) uses the structured
     sketch drawn at t = 0 on both the model and the data and the same FISTA
     (step from the first subproblem) for a given number of iterations.
@@ -111,6 +113,35 @@ def classical_init(st, normal_maps_fn, adjoint_maps_fn, y, x0, V, S, seed, K0, l
     ys = sk.virtual_data(y, st.U) @ St.T
     bs = adjoint_maps_fn(ys, m0)
     return fista_full(lambda v: normal_maps_fn(v, m0), bs, x0, alpha, lam, K0, levels)
+
+
+def compress(st, y, C0):
+    """Alg. 1's initial coil compression: the first C0 virtual maps and the
+    data rotated onto them, (U^H y)[:, :C0] per sample."""
+    return st.vmaps[..., :C0], sk.virtual_data(y, st.U)[:, :C0]
+
+
+def coil_sketch_compressed(normal_maps_fn, adjoint_maps_fn, maps, y, dcf, x0, C0, V, S, seed,
+                           T, K, lam, alpha=None, levels=4, n_pow=30, callback=None, t0=1,
+                           dist="rademacher"):
+    """Algorithm 1 after compressing to the first C0 virtual coils (Alg. 1
+    line 4): the true gradient and the sketches both use the compressed
+    model A_c (maps U^H c truncated to C0) and data y_c; V + S <= C0.
+    Returns (x^T, alpha, state)."""
+    st = SketchState(maps, y, dcf)
+    mc, yc = compress(st, y, C0)
+    bc = adjoint_maps_fn(yc, mc)
+    if alpha is None:
+        m1 = sk.sketch_for_iteration(mc, V, S, seed, 1, dist)[0]
+        alpha = 1.0 / power_iteration(lambda v: normal_maps_fn(v, m1), x0.shape, n_pow)
+    x = np.array(x0, dtype=np.complex128, copy=True)
+    for t in range(t0, t0 + T):
+        d = normal_maps_fn(x, mc) - bc
+        mt = sk.sketch_for_iteration(mc, V, S, seed, t, dist)[0]
+        x = sketched_subproblem(lambda v: normal_maps_fn(v, mt), d, x, alpha, lam, K, levels)
+        if callback is not None:
+            callback(t, x)
+    return x, alpha, st
 
 
 def coil_sketch(normal_maps_fn, maps, y, dcf, b, x0, V, S, seed, T, K, lam,

@@ -159,3 +159,40 @@ def test_classical_init_lowers_the_sketched_objective():
     x1 = recon.classical_init(st, nf, af, y, np.zeros(shape, complex), V, S, seed, 40, lam,
                               alpha, levels=2)
     assert obj(x1) < 0.2 * obj(np.zeros(shape, complex))
+
+
+def test_compression_to_all_coils_changes_nothing():
+    # C0 = C: the rotation onto the virtual coils is unitary, so the
+    # compressed method is Algorithm 1 itself
+    shape, x, maps, mask, y = _small(seed=42, n=16, C=6)
+    C = maps.shape[-1]
+    nf = lambda v, m: cart.normal(v, m, mask)
+    af = lambda yy, m: cart.adjoint(yy.reshape(shape + (m.shape[-1],)), m, mask)
+    b = cart.adjoint(y.reshape(shape + (C,)), maps, mask)
+    x0 = np.zeros(shape, complex)
+    xa, alpha, _ = recon.coil_sketch(nf, maps, y, None, b, x0, 2, 2, 9, 3, 4, 1e-3, levels=2)
+    xb, _, _ = recon.coil_sketch_compressed(nf, af, maps, y, None, x0, C, 2, 2, 9, 3, 4, 1e-3,
+                                            alpha=alpha, levels=2)
+    assert np.linalg.norm(xa - xb) < 1e-10 * np.linalg.norm(xa)
+
+
+def test_compressed_algorithm1_solves_the_compressed_problem():
+    # C0 < C with V = C0, S = 0: the subproblem's gradient N_c(x - x^t) + d is
+    # exactly the compressed problem's N_c x - b_c, so one outer iteration is
+    # plain FISTA on 1/2 ||A_c x - y_c||^2 + lam ||Psi x||_1, iterate for
+    # iterate; that problem differs from the uncompressed one
+    shape, x, maps, mask, y = _small(seed=43, n=16, C=6)
+    C0, lam, K = 4, 1e-3, 60
+    nf = lambda v, m: cart.normal(v, m, mask)
+    af = lambda yy, m: cart.adjoint(yy.reshape(shape + (m.shape[-1],)), m, mask)
+    st = recon.SketchState(maps, y, None)
+    mc, yc = recon.compress(st, y, C0)
+    alpha = 1.0 / recon.power_iteration(lambda v: nf(v, mc), shape)
+    ref = recon.fista_full(lambda v: nf(v, mc), af(yc, mc), np.zeros(shape, complex), alpha, lam,
+                           K, levels=2)
+    xs, _, _ = recon.coil_sketch_compressed(nf, af, maps, y, None, np.zeros(shape, complex), C0,
+                                            C0, 0, 4, 1, K, lam, alpha=alpha, levels=2)
+    assert np.linalg.norm(xs - ref) < 1e-10 * np.linalg.norm(ref)
+    full = recon.fista_full(lambda v: nf(v, maps), af(y, maps), np.zeros(shape, complex), alpha,
+                            lam, K, levels=2)
+    assert np.linalg.norm(full - ref) > 1e-3 * np.linalg.norm(ref)
