@@ -168,6 +168,12 @@ typedef struct {
                         t = 0 on maps and data (S~^0 U^H y per sample), by this
                         many FISTA iterations from x^{t0}; the sketched data
                         buffer ([N][V+S]) is allocated on its first use */
+  int C0;            /* Alg. 1's initial coil compression: 0 < C0 < C rotates the
+                        model and the data onto the PCA virtual coils and keeps
+                        the first C0 (the true gradient and b use them, the
+                        sketches draw over them: V + S <= C0); 0 or >= C keeps
+                        every coil.  Compressed maps [D][C0] and data [N][C0]
+                        are allocated on first use */
 } cs_recon_params;
 
 typedef struct {

@@ -83,6 +83,7 @@ class ReconParams(ctypes.Structure):
         ("reg", ctypes.c_int),
         ("n_cg", ctypes.c_int),
         ("init_iters", ctypes.c_int),
+        ("C0", ctypes.c_int),
     ]
 
 
@@ -363,11 +364,12 @@ class Context:
 
     def recon_run(self, y, mode="sketch", lam=1e-3, T=10, K=5, V=2, S=2, seed=0, t0=1,
                   step=0.0, n_pow=30, reuse_b=False, x=None, x_ref=None, cnn=None,
-                  reg="l1wav", n_cg=5, init_iters=0):
+                  reg="l1wav", n_cg=5, init_iters=0, C0=0):
         """Algorithm 1 (mode "sketch", "learned") or the plain solver ("full")
         with regularizer reg: "l1wav" (FISTA), "l2" (conjugate gradients) or
         "tv" (PDHG with n_cg CG iterations per data-consistency step).
-        init_iters > 0 runs the classical-sketch initialisation first."""
+        init_iters > 0 runs the classical-sketch initialisation first; 0 < C0 < C
+        compresses to the first C0 virtual coils (Alg. 1's compression step)."""
         self._data(y, self.C)
         if x is None:
             x = torch.zeros(self.shape, dtype=torch.complex64, device=self.device)
@@ -381,6 +383,7 @@ class Context:
         p.reg = {"l1wav": CS_REG_L1WAV, "l2": CS_REG_L2, "tv": CS_REG_TV}[reg]
         p.n_cg = int(n_cg)
         p.init_iters = int(init_iters)
+        p.C0 = int(C0)
         p.lam = float(lam)
         p.T, p.K, p.V, p.S = int(T), int(K), int(V), int(S)
         p.seed = int(seed)

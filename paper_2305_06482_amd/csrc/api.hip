@@ -524,7 +524,10 @@ int power_iter(cs_ctx* c, const float2* maps, int ncoil, int n_iter, double* L) 
 int sketch_impl(cs_ctx* c, const float2* y, int V, int S, uint64_t seed, int t, int refresh,
                 float2* smaps, std::vector<int8_t>* signs_out) {
   const int C = c->C;
-  if (V < 0 || S < 0 || V + S < 1 || V + S > C)
+  // within a compressed reconstruction the sketch acts on the first c0_active
+  // virtual coils only
+  const int Ce = c->c0_active > 0 ? c->c0_active : C;
+  if (V < 0 || S < 0 || V + S < 1 || V + S > Ce)
     return fail(c, CS_EINVAL, "sketch sizes: need V >= 0, S >= 0 and 0 < V + S <= C");
   if (!c->have_U || refresh) {
     if (!y) return fail(c, CS_EINVAL, "y is required for the first sketch");
@@ -546,8 +549,8 @@ int sketch_impl(cs_ctx* c, const float2* y, int V, int S, uint64_t seed, int t, 
     CS_TRY(coil_mix(c, c->vmaps, C, 0, V, I.data(), V, smaps, Ch, 0, 1.0f));
   }
   std::vector<int8_t> sg;
-  if (S > 0 && V < C) {
-    const int cols = C - V;
+  if (S > 0 && V < Ce) {
+    const int cols = Ce - V;
     std::vector<double> R((size_t)2 * S * cols, 0.0);
     if (c->sketch_dist == CS_SKETCH_GAUSSIAN) {
       std::vector<double> gv;
@@ -685,6 +688,8 @@ void cs_destroy(cs_ctx* c) {
   for (auto* p : c->img) fr(p);
   fr(c->tvu);
   fr(c->ysk);
+  fr(c->cmaps);
+  fr(c->ycmp);
   for (auto& kv : c->plans) fr(kv.second.tw);
   if (c->host_red) (void)hipHostFree(c->host_red);
   for (auto& r : c->prof_recs) {
@@ -923,6 +928,11 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
   if (p->init_iters < 0 ||
       (p->init_iters > 0 && (l2 || tvr || p->mode == CS_RECON_FULL)))
     return fail(c, CS_EINVAL, "the classical-sketch initialisation is for l1-wavelet Algorithm 1");
+  if (p->C0 < 0) return fail(c, CS_EINVAL, "C0");
+  if (p->C0 > 0 && p->C0 < c->C && p->init_iters > 0)
+    return fail(c, CS_EINVAL, "the classical-sketch initialisation needs C0 = C");
+  if (p->C0 > 0 && p->C0 < c->C && p->mode != CS_RECON_FULL && p->V + p->S > p->C0)
+    return fail(c, CS_EINVAL, "sketch sizes: need V + S <= C0");
   if (p->T < 0 || (p->mode != CS_RECON_FULL && p->K < 1))
     return fail(c, CS_EINVAL, "iteration counts");
   if (st) st->n_warm_accepted = st->n_warm_rejected = 0;
@@ -948,9 +958,52 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
   if (!ev_prep) return fail(c, CS_EHIP, "event creation failed");
   pooled.evs.push_back(ev_prep);
   CS_HIP(c, hipEventRecord(ev_prep, c->stream));
-  if (!p->reuse_b || !c->have_b) {
-    CS_TRY(chunk_loop(c, C, op_adjoint, c->maps, y, b));
+  // Alg. 1's initial coil compression: the model and the data rotated onto
+  // the first C0 PCA virtual coils; the full-coil operator below is then
+  // (fmaps, FC) and the sketches draw over those FC virtual coils
+  const bool compress = p->C0 > 0 && p->C0 < C;
+  struct C0Scope {
+    cs_ctx* c;
+    ~C0Scope() { c->c0_active = 0; }
+  } c0scope{c};
+  const float2* fmaps = c->maps;
+  int FC = C;
+  if (compress) {
+    const int C0 = p->C0;
+    if (!c->have_U) CS_TRY(sketch_impl(c, y, C0, 0, p->seed, p->t0, 0, c->smaps, nullptr));
+    auto grow = [&](float2** buf, size_t* have, size_t need) -> int {
+      if (need <= *have) return CS_OK;
+      if (*buf) CS_HIP(c, hipFree(*buf));
+      *buf = nullptr;
+      *have = 0;
+      CS_HIP(c, hipMalloc(buf, sizeof(float2) * need));
+      *have = need;
+      return CS_OK;
+    };
+    CS_TRY(grow(&c->cmaps, &c->cmaps_elems, (size_t)c->D * C0));
+    CS_TRY(grow(&c->ycmp, &c->ycmp_elems, (size_t)std::max(1LL, c->N) * C0));
+    // first C0 rows of U^H: M[j][cc] = conj(U[cc][j])
+    std::vector<double> M((size_t)2 * C0 * C);
+    for (int j = 0; j < C0; ++j)
+      for (int cc = 0; cc < C; ++cc) {
+        M[2 * (j * C + cc)] = c->U[2 * (cc * C + j)];
+        M[2 * (j * C + cc) + 1] = -c->U[2 * (cc * C + j) + 1];
+      }
+    std::vector<double> I((size_t)2 * C0 * C0, 0.0);
+    for (int j = 0; j < C0; ++j) I[2 * (j * C0 + j)] = 1.0;
+    CS_TRY(coil_mix(c, c->vmaps, C, 0, C0, I.data(), C0, c->cmaps, C0, 0, 1.0f));
+    CS_TRY(coil_mix_rows(c, c->N, y, C, 0, C, M.data(), C0, c->ycmp, C0, 0, 1.0f));
+    c->c0_active = C0;
+    fmaps = c->cmaps;
+    FC = C0;
+  }
+  if (!p->reuse_b || !c->have_b || c->b_c0 != FC) {
+    if (compress)
+      CS_TRY(chunk_loop(c, FC, op_adjoint, fmaps, c->ycmp, b));
+    else
+      CS_TRY(chunk_loop(c, C, op_adjoint, c->maps, y, b));
     c->have_b = true;
+    c->b_c0 = FC;
   }
   const int Ch = p->V + p->S;
   const int n_pow = p->n_pow > 0 ? p->n_pow : 30;
@@ -967,7 +1020,7 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
     }
   } else if (alpha <= 0 && !l2 && !tvr) {
     double L = 0;
-    CS_TRY(power_iter(c, c->maps, C, n_pow, &L));
+    CS_TRY(power_iter(c, fmaps, FC, n_pow, &L));
     nfull += n_pow + 1;
     alpha = 1.0 / L;
   }
@@ -1123,11 +1176,11 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
     };
     if (p->mode == CS_RECON_FULL) {
       CS_TRY(vec_copy(c, rhs0, b, D));
-      CS_TRY(pdhg(c->maps, C, p->T, 0, &nfull, 0));
+      CS_TRY(pdhg(fmaps, FC, p->T, 0, &nfull, 0));
     } else {
       for (int it = 0; it < p->T; ++it) {
         const int t = p->t0 + it;
-        CS_TRY(timed(0, [&] { return op_normal(c, c->maps, C, x, g); }));
+        CS_TRY(timed(0, [&] { return op_normal(c, fmaps, FC, x, g); }));
         ++nfull;
         CS_TRY(vec_axpby(c, d, 1.f, g, -1.f, b, D));
         if (it > 0)
@@ -1156,11 +1209,11 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
     double rr[2] = {0, 0};
     for (int it = 0; it < p->T; ++it) {
       if (it == 0) {
-        CS_TRY(cg_solve(c, c->maps, C, p->lam, x, false, r, pd, q, 1, 0, &timed_fn, &n));
+        CS_TRY(cg_solve(c, fmaps, FC, p->lam, x, false, r, pd, q, 1, 0, &timed_fn, &n));
         nfull += n;
         CS_TRY(vec_dot(c, r, r, D, rr));
       } else if (rr[0] > 0.0) {
-        CS_TRY(timed(0, [&] { return op_normal(c, c->maps, C, pd, q); }));
+        CS_TRY(timed(0, [&] { return op_normal(c, fmaps, FC, pd, q); }));
         ++nfull;
         CS_TRY(vec_axpby(c, q, 1.f, q, p->lam, pd, D));
         double pq[2];
@@ -1188,7 +1241,7 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
     float2* q = c->img[5];
     for (int it = 0; it < p->T; ++it) {
       const int t = p->t0 + it;
-      CS_TRY(timed(0, [&] { return op_normal(c, c->maps, C, x, g); }));
+      CS_TRY(timed(0, [&] { return op_normal(c, fmaps, FC, x, g); }));
       ++nfull;
       CS_TRY(vec_axpby(c, d, 1.f, g, -1.f, b, D));
       if (it > 0)
@@ -1208,7 +1261,7 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
     CS_TRY(vec_copy(c, z, x, D));
     double tau = 1.0;
     for (int it = 0; it < p->T && rc == CS_OK; ++it) {
-      CS_TRY(timed(0, [&] { return op_normal(c, c->maps, C, z, g); }));
+      CS_TRY(timed(0, [&] { return op_normal(c, fmaps, FC, z, g); }));
       ++nfull;
       CS_TRY(vec_fista_step(c, v, z, a, g, -1.f, b, D));
       CS_TRY(timed(2, [&] { return prox_l1(c, v, tau_l, xn); }));
@@ -1257,7 +1310,7 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
     for (int it = 0; it < p->T; ++it) {
       const int t = p->t0 + it;
       // true gradient d = A^H (A x^t - y) = A^H A x^t - b (Alg. 1 line 9)
-      CS_TRY(timed(0, [&] { return op_normal(c, c->maps, C, x, g); }));
+      CS_TRY(timed(0, [&] { return op_normal(c, fmaps, FC, x, g); }));
       ++nfull;
       CS_TRY(vec_axpby(c, d, 1.f, g, -1.f, b, D));
       // sketched model A_S^t (Alg. 1 line 10)

@@ -128,6 +128,12 @@ struct cs_ctx {
   float2* tvu = nullptr;          // [ndim][D] PDHG dual variable of the TV term
   float2* ysk = nullptr;          // [N][C^] sketched data of the classical initialisation
   size_t ysk_elems = 0;           // (allocated on its first use)
+  float2* cmaps = nullptr;        // [D][C0] compressed virtual maps (initial compression)
+  size_t cmaps_elems = 0;
+  float2* ycmp = nullptr;         // [N][C0] compressed data
+  size_t ycmp_elems = 0;
+  int c0_active = 0;              // > 0 inside a compressed reconstruction
+  int b_c0 = 0;                   // coil count b = A^H y was formed with
 
   // sketch cache
   bool have_U = false;

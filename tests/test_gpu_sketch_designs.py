@@ -171,3 +171,56 @@ def test_classical_init_matches_oracle(kind):
     assert e < 1e-3, e
     assert res.n_sketch_applies == K0 + T * K
     ctx.close()
+
+
+@pytest.mark.parametrize("kind", ["cart", "radial"])
+def test_initial_compression_matches_oracle(kind):
+    """Alg. 1 after compressing to the first C0 = 6 of 8 virtual coils (model
+    and data), against the oracle."""
+    dev()
+    import torch
+    from paper_2305_06482_amd import Context
+    from oracle import nufft
+    case(f"initial coil compression C0=6, {kind}")
+    T, K, C0, V, S = 3, 5, 6, 3, 1
+    if kind == "cart":
+        p = synth.make_cart_small()
+        C = p.n_coils
+        y = cart.forward(p.x_true, p.maps, p.mask) + p.noise.reshape(p.shape + (C,)) * \
+            p.mask[..., None]
+        y = y.astype(np.complex64).astype(np.complex128)
+        maps = p.maps.astype(np.complex64).astype(np.complex128)
+        nf = lambda v, m: cart.normal(v, m, p.mask)
+        af = lambda yy, m: cart.adjoint(yy.reshape(p.shape + (m.shape[-1],)), m, p.mask)
+        ctx = Context(p.shape, C, "cart")
+        ctx.set_operator(t(maps), mask=t(p.mask, torch.uint8))
+        y2, dcf, yt = y.reshape(-1, C), None, t(y)
+    else:
+        p = synth.make_radial(64, 48, 8, 2, 2, seed_base=7500)
+        C = p.n_coils
+        c32, w32 = p.coords.astype(np.float32), p.dcf.astype(np.float32)
+        maps = p.maps.astype(np.complex64).astype(np.complex128)
+        plan = nufft.Plan(p.shape, c32.astype(np.float64), w32.astype(np.float64))
+        y2 = (plan.forward(p.x_true, maps) + p.noise * np.sqrt(w32)[:, None]
+              ).astype(np.complex64).astype(np.complex128)
+        nf = lambda v, m: plan.normal(v, m)
+        af = lambda yy, m: plan.adjoint(yy, m)
+        dcf = w32.astype(np.float64)
+        ctx = Context(p.shape, C, "noncart", nsamp=c32.shape[0], wav_levels=4)
+        ctx.set_operator(t(maps.astype(np.complex64)), coords=t(c32), dcf=t(w32))
+        yt = t(y2)
+    xr, alpha, _ = orecon.coil_sketch_compressed(nf, af, maps, y2, dcf,
+                                                 np.zeros(p.shape, complex), C0, V, S, p.seed,
+                                                 T, K, p.lam)
+    res = ctx.recon_run(yt, mode="sketch", lam=p.lam, T=T, K=K, V=V, S=S, seed=p.seed,
+                        step=alpha, C0=C0)
+    e = orecon.nrmse(h(res.x), xr)
+    assert e < 1e-3, e
+    # the next uncompressed call recomputes b = A^H y for all coils
+    full = ctx.recon_run(yt, mode="sketch", lam=p.lam, T=1, K=K, V=V, S=S, seed=p.seed,
+                         step=alpha, reuse_b=True)
+    b = af(y2, maps)
+    xr1, _, _ = orecon.coil_sketch(nf, maps, y2, dcf, b, np.zeros(p.shape, complex), V, S,
+                                   p.seed, 1, K, p.lam, alpha=alpha)
+    assert orecon.nrmse(h(full.x), xr1) < 1e-3
+    ctx.close()
