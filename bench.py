@@ -49,6 +49,44 @@ def model_bytes_normal(geom, ncoil):
     return ncoil * per_coil + 2 * 8 * D + 16 * N
 
 
+def min_bytes_normal(D, N, ndim, ncoil):
+    """Compulsory HBM bytes of one normal apply: x read and the result
+    written once, each coil map read twice (the FFT between the forward and
+    the adjoint multiply is a global dependency), the coordinates and the
+    density weights read once (complex64 = 8 B, float32 = 4 B)."""
+    return 8 * (2 * D + 2 * ncoil * D) + 4 * (ndim + 1) * N
+
+
+def model_bytes_normal_2d(ny, nx, my, mx, N, ncoil):
+    """Modelled HBM bytes of one 2D NUFFT normal apply: per coil the maps
+    twice, one write and read of the intermediate grid per axis pass (the
+    first pass pads one axis, my x nx; the second writes the my x mx grid),
+    the interpolation read and the spreading write of the grid; plus x, the
+    result and the coordinates and weights."""
+    D, M = ny * nx, my * mx
+    return ncoil * 8 * (2 * D + 4 * my * nx + 4 * M) + 2 * 8 * D + 12 * N
+
+
+def hbm_copy_bandwidth(nbytes=2 << 30, reps=10):
+    """Achievable HBM bandwidth of a plain device-to-device copy (bytes read
+    plus bytes written, over the mean of `reps` copies)."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * nbytes, "ms": ms, "GB/s": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
 def kernel_bytes(geom, cb):
     """Algorithmic bytes per launch of the main kernels for a coil chunk cb."""
     nz, ny, nx, mz, my, mx, N = geom
@@ -278,7 +316,7 @@ def train_warm_start(args, log, n_problems=6, T=8, K=100, steps=600, lam=5e-4, V
     return net, info
 
 
-def cartesian_tta(p, args, log):
+def cartesian_tta(p, args, log, outer_iters=None):
     """Time to accuracy on a Cartesian problem (its own context)."""
     import numpy as np
     import torch
@@ -292,13 +330,53 @@ def cartesian_tta(p, args, log):
     ctx.set_operator(maps, mask=mask)
     y = ctx.sense_apply(maps, dt(p.x_true, torch.complex64))
     y += dt(p.noise.reshape(p.shape + (C,)), torch.complex64) * mask[..., None]
+    if outer_iters is None:
+        outer_iters = [("sketched", 5, 800, "sketch"),
+                       ("sketched", 20, 250, "sketch"),
+                       ("sketched", 20, 250, "sketch", p.V + p.S - 1, 1)]
     res = time_to_accuracy(ctx, y, p, args, log, ref_iters=20000, full_iters=4000,
-                           outer_iters=[("sketched", 5, 800, "sketch"),
-                                        ("sketched", 20, 250, "sketch"),
-                                        ("sketched", 20, 250, "sketch", p.V + p.S - 1, 1)],
-                           chunk=1000)
+                           outer_iters=outer_iters, chunk=1000)
     ctx.close()
     return res
+
+
+def cartesian_tta_seeds(first, args, log, seeds):
+    """Time to accuracy on the 320 x 320 Cartesian problem over `seeds`
+    independent draws of phantom, maps, mask, noise and sketch seed (the
+    first is the run `first`, the others use held-out seed bases): full-coil
+    FISTA against Algorithm 1 with K = 20, V = C^ - 1, S = 1.  Reports the
+    times per draw and the median and range of the speed-up."""
+    import numpy as np
+    import synth
+
+    def pick(r):
+        return r["full_coil"], next(v for k, v in r.items()
+                                    if k.startswith("sketched_K20_V") and k.endswith("S1"))
+    runs = [pick(first)]
+    bases = [2000]
+    for k in range(1, seeds):
+        base = 2000 + 100 * k
+        pc = synth.make_cart_clinical(seed_base=base)
+        r = cartesian_tta(pc, args, log, outer_iters=[("sketched", 20, 250, "sketch",
+                                                       pc.V + pc.S - 1, 1)])
+        runs.append(pick(r))
+        bases.append(base)
+    out = {"seed_bases": bases}
+    for thr in TTA_THRESHOLDS:
+        key = f"{thr:g}"
+        f = [a[key]["total_ms"] if a[key] else None for a, _ in runs]
+        s = [b[key]["total_ms"] if b[key] else None for _, b in runs]
+        ratio = [fa / sa for fa, sa in zip(f, s) if fa is not None and sa is not None]
+        out[key] = {"full_ms": f, "sketched_ms": s, "both_reached": len(ratio),
+                    "speedup_median": float(np.median(ratio)) if ratio else None,
+                    "speedup_min": min(ratio) if ratio else None,
+                    "speedup_max": max(ratio) if ratio else None}
+    log("cart320 over seeds: " + ", ".join(
+        f"{k}: speed-up median {v['speedup_median'] and round(v['speedup_median'], 2)} "
+        f"[{v['speedup_min'] and round(v['speedup_min'], 2)}, "
+        f"{v['speedup_max'] and round(v['speedup_max'], 2)}] ({v['both_reached']} reached)"
+        for k, v in out.items() if k != "seed_bases"))
+    return out
 
 
 def gfactor_bench(args, log, n=256, C=8, accel=3, trials=60, lam=1e-2, sigma=1e-2,
@@ -547,8 +625,18 @@ def batched_bench(args, log, T=3, K=5):
     torch.cuda.synchronize()
     log(f"batched: {len(sl)} slices set up in {time.time() - t0:.1f} s, "
         f"spreading shapes {tuned}")
+    # modelled bytes of the normal applies of one outer iteration of every
+    # slice: one full-coil apply and K sketched applies
+    apply_bytes = 0
+    for p, ctx, _, _ in sl:
+        _, my, mx = ctx.grid_shape()
+        ny, nx = p.shape
+        N = p.coords.shape[0]
+        apply_bytes += (model_bytes_normal_2d(ny, nx, my, mx, N, p.n_coils)
+                        + K * model_bytes_normal_2d(ny, nx, my, mx, N, p.V + p.S))
     res = {"slices": len(sl), "samples_per_coil_total": int(sum(p.coords.shape[0]
                                                               for p, *_ in sl)),
+           "apply_model_bytes_per_outer_iteration": int(apply_bytes),
            "coil_samples_total": int(sum(p.coords.shape[0] * p.n_coils for p, *_ in sl)),
            "outer_iterations": T, "K": K, "spread_shapes": {str(k): v for k, v in tuned.items()}}
     xs = {}
@@ -568,6 +656,10 @@ def batched_bench(args, log, T=3, K=5):
         xs[key] = x
     res["graph_equals_eager"] = all(torch.equal(a, b) for a, b in zip(xs["eager"], xs["graph"]))
     res["graph_speedup"] = res["eager_ms_per_outer_iteration"] / res["graph_ms_per_outer_iteration"]
+    # a lower bound on the applies' bandwidth: the time also holds the prox,
+    # the coil mixing and the host's launch work
+    best = min(res["eager_ms_per_outer_iteration"], res["graph_ms_per_outer_iteration"])
+    res["apply_model_GBs_lower_bound"] = apply_bytes / (best * 1e-3) / 1e9
     log(f"batched: eager {res['eager_ms_per_outer_iteration']:.1f} ms, graph "
         f"{res['graph_ms_per_outer_iteration']:.1f} ms per outer iteration "
         f"({res['graph_nodes']} graph nodes), identical {res['graph_equals_eager']}")
@@ -624,6 +716,11 @@ def main():
     # workload's default 5e-4 plain FISTA is still far from its minimizer
     # after thousands of iterations, which leaves x_inf undefined at 5%
     ap.add_argument("--tta-lam", type=float, default=0.02)
+    ap.add_argument("--tta-cart-seeds", type=int, default=5,
+                    help="draws of the 320x320 Cartesian problem for the time-to-accuracy "
+                         "spread")
+    ap.add_argument("--no-cones-tta", action="store_true",
+                    help="time to accuracy on the Cartesian problems only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -717,6 +814,9 @@ def main():
     ms_sketch = sum(r.ms_sketch for r in results)
     b_sk = model_bytes_normal(geom, Ch)
     b_full = model_bytes_normal(geom, C)
+    D3 = nz * ny * nx
+    bmin_sk = min_bytes_normal(D3, geom[6], 3, Ch)
+    bmin_full = min_bytes_normal(D3, geom[6], 3, C)
     gbs = b_sk * n_sk / (ms_sk * 1e-3) / 1e9
     gbs_full = b_full * n_full / (ms_full * 1e-3) / 1e9
 
@@ -773,10 +873,15 @@ def main():
                               "sketched_normal": ms_sk / args.steps,
                               "prox": ms_prox / args.steps, "sketch": ms_sketch / args.steps},
         "model_bytes": {"sketched": b_sk, "full": b_full},
+        "min_bytes": {"sketched": bmin_sk, "full": bmin_full},
+        "min_GBs": {"sketched": round(bmin_sk * n_sk / (ms_sk * 1e-3) / 1e9, 1),
+                    "full": round(bmin_full * n_full / (ms_full * 1e-3) / 1e9, 1)},
         "device_memory": mem,
         "kernels": kern,
         "roofline": roof,
     }
+    out["hbm_copy"] = hbm_copy_bandwidth()
+    log(f"plain device copy: {out['hbm_copy']['GB/s']:.0f} GB/s")
     cpu_ref = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
@@ -798,25 +903,29 @@ def main():
     if not args.no_tta:
         log("time-to-accuracy runs")
         tta = {"thresholds": list(TTA_THRESHOLDS)}
-        net, tinfo = train_warm_start(args, log, lam=args.tta_lam)
-        tta["warm_start_training"] = tinfo
-        tta[p.name] = time_to_accuracy(ctx, y, p, args, log, args.tta_ref_iters,
-                                       args.tta_full_iters,
-                                       [("sketched", args.K, args.tta_outer_iters, "sketch"),
-                                        ("sketched", 20, 60, "sketch"),
-                                        # the design the paper's sketching
-                                        # experiments favour: V = C^ - 1, S = 1
-                                        ("sketched", 20, 60, "sketch", Ch - 1, 1),
-                                        # longer subproblem solves: momentum
-                                        # restarts less often
-                                        ("sketched", 50, 24, "sketch", Ch - 1, 1),
-                                        ("sketched", 100, 12, "sketch", Ch - 1, 1),
-                                        ("sketched_learned", 100, 12, "learned", Ch - 1, 1)],
-                                       args.tta_chunk, cnn=net, lam=args.tta_lam, restart=100)
-        net.close()
+        if not args.no_cones_tta:
+            net, tinfo = train_warm_start(args, log, lam=args.tta_lam)
+            tta["warm_start_training"] = tinfo
+            tta[p.name] = time_to_accuracy(ctx, y, p, args, log, args.tta_ref_iters,
+                                           args.tta_full_iters,
+                                           [("sketched", args.K, args.tta_outer_iters, "sketch"),
+                                            ("sketched", 20, 60, "sketch"),
+                                            # the design the paper's sketching
+                                            # experiments favour: V = C^ - 1, S = 1
+                                            ("sketched", 20, 60, "sketch", Ch - 1, 1),
+                                            # longer subproblem solves: momentum
+                                            # restarts less often
+                                            ("sketched", 50, 24, "sketch", Ch - 1, 1),
+                                            ("sketched", 100, 12, "sketch", Ch - 1, 1),
+                                            ("sketched_learned", 100, 12, "learned", Ch - 1, 1)],
+                                           args.tta_chunk, cnn=net, lam=args.tta_lam, restart=100)
+            net.close()
         if not args.small:
             for pc in (synth.make_cart_small(), synth.make_cart_clinical()):
                 tta[pc.name] = cartesian_tta(pc, args, log)
+            if args.tta_cart_seeds > 1:
+                tta["cart320_seeds"] = cartesian_tta_seeds(tta["cart320"], args, log,
+                                                           args.tta_cart_seeds)
         out["time_to_accuracy"] = tta
     print(json.dumps(out), flush=True)
     ctx.close()

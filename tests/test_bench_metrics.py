@@ -33,3 +33,25 @@ def test_ssim_of_a_scaled_image():
     import synth
     ref = np.abs(synth.phantom((32, 32), 4))
     assert bench.image_quality(0.5 * ref, ref)["ssim"] < bench.image_quality(0.9 * ref, ref)["ssim"] < 1.0
+
+
+def test_byte_models_of_the_normal_apply():
+    # 3D cones, 192 x 192 x 128, 9.216 M samples, grid 240 x 240 x 160:
+    # 1.129 GB compulsory and 9.764 GB modelled for 12 coils, 2.64 GB and
+    # 25.67 GB for 32 (the per-stage tally of the workload)
+    D, N = 192 * 192 * 128, 9216000
+    geom = (128, 192, 192, 160, 240, 240, N)
+    assert abs(bench.min_bytes_normal(D, N, 3, 12) / 1e9 - 1.129) < 1e-3
+    assert abs(bench.model_bytes_normal(geom, 12) / 1e9 - 9.764) < 1e-3
+    assert abs(bench.min_bytes_normal(D, N, 3, 32) / 1e9 - 2.64) < 5e-3
+    assert abs(bench.model_bytes_normal(geom, 32) / 1e9 - 25.67) < 5e-3
+    # 2D, n = 256 on a 320 x 320 grid, stage by stage per coil: maps read
+    # twice; forward pass 1 writes 320 x 256, pass 2 reads it and writes the
+    # grid; interpolation reads the grid, spreading writes it; the adjoint
+    # passes mirror the forward ones
+    n, m, N2, C = 256, 320, 402 * 512, 5
+    stages = [2 * n * n, m * n, m * n + m * m, m * m, m * m, m * m + m * n, m * n]
+    per_coil = 8 * sum(stages)
+    want = C * per_coil + 2 * 8 * n * n + 12 * N2
+    assert bench.model_bytes_normal_2d(n, n, m, m, N2, C) == want
+    assert bench.min_bytes_normal(n * n, N2, 2, C) == 8 * n * n * (2 + 2 * C) + 12 * N2
