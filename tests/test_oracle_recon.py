@@ -106,6 +106,32 @@ def test_fixed_point_of_outer_iteration():
         assert np.linalg.norm(x1 - xinf) < 1e-6 * np.linalg.norm(xinf)
 
 
+def test_fista_matches_its_three_sequence_form():
+    # Beck and Teboulle's FISTA written the other way: x_k = prox(y_k - a g(y_k)),
+    # v_k = x_{k-1} + tau_k (x_k - x_{k-1}), y_{k+1} = (1 - 1/tau_{k+1}) x_k +
+    # v_k / tau_{k+1}, with tau_{k+1} the positive root of t^2 - t = tau_k^2.
+    # Expanding y_{k+1} gives the momentum form the oracle uses, so the
+    # iterates must agree; a wrong momentum or tau sequence breaks this.
+    from oracle import wavelet as wv
+    shape, x, maps, mask, y = _small(C=4)
+    b = cart.adjoint(y.reshape(shape + (-1,)), maps, mask)
+    N = lambda v: cart.normal(v, maps, mask)
+    a, lam, K = 0.8, 5e-3, 25
+    want = []
+    recon.fista_full(N, b, np.zeros(shape, complex), a, lam, K, levels=2,
+                     callback=lambda k, xk: want.append(xk.copy()))
+    xprev = np.zeros(shape, complex)
+    yk = xprev.copy()
+    tau = 1.0
+    for k in range(K):
+        xk = wv.prox_l1_wavelet(yk - a * (N(yk) - b), a * lam, 2)
+        v = xprev + tau * (xk - xprev)
+        tau = max(np.roots([1.0, -1.0, -tau * tau]).real)
+        yk = (1.0 - 1.0 / tau) * xk + v / tau
+        xprev = xk
+        assert np.max(np.abs(xk - want[k])) < 1e-12 * np.max(np.abs(want[k]))
+
+
 def test_power_iteration_full_mask_closed_form():
     shape = (16, 16)
     maps = _rand(shape + (3,), 5)

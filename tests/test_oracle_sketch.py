@@ -58,6 +58,24 @@ def test_pca_properties():
         assert abs(U[i, j].imag) < 1e-14 and U[i, j].real > 0
 
 
+def test_virtual_maps_and_virtual_data_describe_one_measurement():
+    # the coil rotation commutes with the per-coil operator: measuring x with
+    # the virtual maps U^H c gives the virtual data U^H k of the same x, for
+    # the Cartesian and the non-Cartesian operator
+    shape, x, maps, mask, y = _problem(11, C=5)
+    C = maps.shape[-1]
+    lam, U = sk.pca(sk.covariance(y))
+    vm = sk.virtual_maps(maps, U)
+    a = cart.forward(x, vm, mask).reshape(-1, C)
+    b = sk.virtual_data(y, U)
+    assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(b))
+    coords = synth.radial_traj(24, 6)
+    plan = nufft.Plan(shape, coords, synth.radial_dcf(coords, 24))
+    a = plan.forward(x, vm)
+    b = sk.virtual_data(plan.forward(x, maps), U)
+    assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(b))
+
+
 def test_rotation_invariance_cartesian_and_nufft():
     shape, x, maps, mask, y = _problem(5)
     lam, U = sk.pca(sk.covariance(y))
