@@ -167,6 +167,58 @@ def soft_without_floor(w, tau):
     return w * scale
 
 
+def pdhg_without_extrapolation(prox_g, x0, lam, n_iter, n_dim, callback=None):
+    tau, sigma = tv.steps(n_dim)
+    x = np.array(x0, dtype=np.complex128, copy=True)
+    u = np.zeros((n_dim,) + x.shape, dtype=np.complex128)
+    for _ in range(n_iter):
+        u = tv.clip(u + sigma * tv.grad(x), lam)
+        x = prox_g(x - tau * tv.grad_adj(u), tau, x)
+    return x
+
+
+def classical_init_data_unsketched(st, normal_maps_fn, adjoint_maps_fn, y, x0, V, S, seed, K0,
+                                   lam, alpha, levels=4, dist="rademacher"):
+    # the model is sketched but the data only rotated and truncated
+    m0, _ = sketch.sketch_for_iteration(st.vmaps, V, S, seed, 0, dist)
+    ys = sketch.virtual_data(y, st.U)[:, :V + S]
+    return recon.fista_full(lambda v: normal_maps_fn(v, m0), adjoint_maps_fn(ys, m0), x0,
+                            alpha, lam, K0, levels)
+
+
+def compress_data_unrotated(st, y, C0):
+    return st.vmaps[..., :C0], np.asarray(y)[:, :C0]
+
+
+def l2_sketch_without_lam_x(normal_maps_fn, maps, y, dcf, b, x0, V, S, seed, T, K, lam, t0=1,
+                            callback=None, dist="rademacher"):
+    # the subproblem's right-hand side loses the -lam x^t term
+    st = recon.SketchState(maps, y, dcf)
+    x = np.array(x0, dtype=np.complex128, copy=True)
+    for t in range(t0, t0 + T):
+        d = normal_maps_fn(x, maps) - b
+        mt = st.maps_for(V, S, seed, t, dist)
+        x = x + l2.cg(lambda v: normal_maps_fn(v, mt) + lam * v, -d, np.zeros_like(x), K)
+    return x, st
+
+
+def pdhg_sketch_with_plus_d(normal_maps_fn, maps, y, dcf, b, x0, V, S, seed, T, K, lam, n_cg,
+                            t0=1, callback=None, dist="rademacher"):
+    # the subproblem's linear term enters with the wrong sign
+    st = recon.SketchState(maps, y, dcf)
+    x = np.array(x0, dtype=np.complex128, copy=True)
+    for t in range(t0, t0 + T):
+        d = normal_maps_fn(x, maps) - b
+        mt = st.maps_for(V, S, seed, t, dist)
+        xt = x.copy()
+        nxt = normal_maps_fn(xt, mt)
+
+        def prox(v, tau, xs):
+            return l2.cg(lambda w: normal_maps_fn(w, mt) + w / tau, nxt + d + v / tau, xs, n_cg)
+        x = tv.pdhg(prox, xt, lam, K, x.ndim)
+    return x, st
+
+
 def conv3d_mirrored_taps(x, W, b):
     # tap (dz, dy, dx) reads the mirrored offset: a correlation turned into a
     # convolution
@@ -224,6 +276,16 @@ CASES = [
      [p_wav.test_unitary_2d_3d, p_wav.test_dense_matrix_orthogonal]),
     ("soft threshold without max(0, .)", wavelet, "soft", soft_without_floor,
      [p_wav.test_soft_threshold_closed_form]),
+    ("PDHG without the extrapolation", tv, "pdhg", pdhg_without_extrapolation,
+     [p_tv.test_pdhg_on_the_bilinear_saddle_problem_reaches_the_mean]),
+    ("classical initialisation with unsketched data", recon, "classical_init",
+     classical_init_data_unsketched, [p_recon.test_classical_init_fits_noise_free_sketched_data]),
+    ("compression rotates the maps but not the data", recon, "compress",
+     compress_data_unrotated, [p_recon.test_compression_to_all_coils_changes_nothing]),
+    ("l2 subproblem without -lam x^t", l2, "l2_sketch", l2_sketch_without_lam_x,
+     [p_l2.test_sketch_with_all_coils_is_one_newton_step]),
+    ("TV subproblem with +d", tv, "pdhg_sketch", pdhg_sketch_with_plus_d,
+     [p_tv.test_sketch_with_all_coils_matches_the_plain_solver]),
     ("convolution with mirrored taps", cnn, "conv3d", conv3d_mirrored_taps,
      [p_cnn.test_delta_kernel_is_identity_and_shift, p_cnn.test_conv_matches_brute_force_sum]),
 ]

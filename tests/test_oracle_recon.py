@@ -187,6 +187,27 @@ def test_classical_init_lowers_the_sketched_objective():
     assert obj(x1) < 0.2 * obj(np.zeros(shape, complex))
 
 
+def test_classical_init_fits_noise_free_sketched_data():
+    # noise-free data y = A x_true: sketching the data gives the sketched
+    # model's data of x_true (the coil mixing commutes with the operator), so
+    # with lam = 0 the initialisation must drive the sketched residual
+    # S^0 A (x^1 - x_true) towards zero
+    shape, C, V, S, seed = (16, 16), 6, 2, 2, 5
+    xt = synth.phantom(shape, 43)
+    maps = synth.coil_maps(shape, C, 44)
+    mask = synth.mask_1d_vd(16, 16, 45, n_center=4, accel=2)
+    y = cart.forward(xt, maps, mask).reshape(-1, C)
+    nf = lambda v, m: cart.normal(v, m, mask)
+    af = lambda yy, m: cart.adjoint(yy.reshape(shape + (m.shape[-1],)), m, mask)
+    st = recon.SketchState(maps, y, None)
+    m0 = sk.sketch_for_iteration(st.vmaps, V, S, seed, 0)[0]
+    alpha = 1.0 / recon.power_iteration(lambda v: nf(v, m0), shape)
+    x1 = recon.classical_init(st, nf, af, y, np.zeros(shape, complex), V, S, seed, 500, 0.0,
+                              alpha, levels=2)
+    r = cart.forward(x1 - xt, m0, mask)
+    assert np.linalg.norm(r) < 2e-3 * np.linalg.norm(cart.forward(xt, m0, mask))
+
+
 def test_compression_to_all_coils_changes_nothing():
     # C0 = C: the rotation onto the virtual coils is unitary, so the
     # compressed method is Algorithm 1 itself

@@ -67,6 +67,18 @@ def test_pdhg_denoises_a_periodic_step_to_its_closed_form():
     assert np.max(np.abs(x - ref)) < 1e-6
 
 
+def test_pdhg_on_the_bilinear_saddle_problem_reaches_the_mean():
+    # G = 0 and a dual radius that no iterate reaches: min_x max_u <T x, u>.
+    # Its primal solutions are the constant images, and the primal update
+    # x - tau T^H u keeps the mean of x (T^H u sums to zero), so PDHG must
+    # converge to the constant image at the mean of x^0.  This takes the
+    # extrapolation xbar = 2 x_new - x; without it the iteration circles.
+    g = np.random.default_rng(9)
+    x0 = g.standard_normal((8, 8)) + 1j * g.standard_normal((8, 8))
+    x = tv.pdhg(lambda v, tau, xs: v, x0, 1e6, 1000, 2)
+    assert np.max(np.abs(x - x0.mean())) < 1e-9 * np.max(np.abs(x0))
+
+
 def test_sketch_with_all_coils_matches_the_plain_solver():
     # V = C, S = 0: the subproblem's quadratic is the full data term, so one
     # outer iteration with a long inner solve reaches the plain minimizer
