@@ -59,3 +59,25 @@ def test_create_rejects_bad_geometry_without_gpu():
     g.kwidth = 6
     g.sigma = 1.25
     assert lib.cs_create(ctypes.byref(g), None, ctypes.byref(out)) == -2
+
+
+def test_every_entry_point_rejects_null_handles_without_gpu():
+    # null context / network / batch handles and null buffers: every call
+    # returns CS_EINVAL (-1) before any device work; destroy is a no-op and
+    # the error strings stay readable
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    from paper_2305_06482_amd import binding
+    lib = binding.load()
+    ints = (ctypes.c_int, ctypes.c_long, ctypes.c_longlong, ctypes.c_uint64, ctypes.c_size_t)
+    for name in declared():
+        f = getattr(lib, name)
+        args = [1 if t in ints else 0.5 if t in (ctypes.c_float, ctypes.c_double) else None
+                for t in (f.argtypes or [])]
+        r = f(*args)
+        if f.restype is ctypes.c_int:
+            assert r == -1, name
+        elif f.restype is ctypes.c_char_p:
+            assert isinstance(r, bytes), name
+        elif f.restype is None:
+            assert r is None, name
