@@ -124,8 +124,8 @@ def compress(st, y, C0):
 def coil_sketch_compressed(normal_maps_fn, adjoint_maps_fn, maps, y, dcf, x0, C0, V, S, seed,
                            T, K, lam, alpha=None, levels=4, n_pow=30, callback=None, t0=1,
                            dist="rademacher"):
-    """Algorithm 1 after compressing to the first C0 virtual coils (Alg. 1
-    line 4): the true gradient and the sketches both use the compressed
+    """Algorithm 1 after its initial compression to the first C0 virtual
+    coils: the true gradient and the sketches both use the compressed
     model A_c (maps U^H c truncated to C0) and data y_c; V + S <= C0.
     Returns (x^T, alpha, state)."""
     st = SketchState(maps, y, dcf)

@@ -3,8 +3,8 @@
 Sec. 2.3.2 (Eqs. 11-13): the sketch S^t = S~^t (x) I_N mixes coils only, so
 A_S^t = W^1/2 F C_S^t with sketched maps c^[d] = S~^t c[d] at every pixel d.
 Sec. 2.3.3: S~^t = blkdiag(I_V, S~_S^t), where the V rows keep the
-high-energy virtual coils obtained by PCA coil compression (Sec. 3.1, Alg. 1
-line 4) and S~_S^t in R^{S x (C-V)} has i.i.d. random entries
+high-energy virtual coils obtained by PCA coil compression (Sec. 3.1, Alg. 1)
+and S~_S^t in R^{S x (C-V)} has i.i.d. random entries
 (Rademacher, Sec. 3.2).
 
 Readings:

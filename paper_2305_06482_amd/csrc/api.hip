@@ -1309,11 +1309,11 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
     };
     for (int it = 0; it < p->T; ++it) {
       const int t = p->t0 + it;
-      // true gradient d = A^H (A x^t - y) = A^H A x^t - b (Alg. 1 line 9)
+      // true gradient d = A^H (A x^t - y) = A^H A x^t - b (Alg. 1, true gradient)
       CS_TRY(timed(0, [&] { return op_normal(c, fmaps, FC, x, g); }));
       ++nfull;
       CS_TRY(vec_axpby(c, d, 1.f, g, -1.f, b, D));
-      // sketched model A_S^t (Alg. 1 line 10)
+      // sketched model A_S^t (Alg. 1, per-iteration sketch)
       if (it > 0)
         CS_TRY(timed(3, [&] {
           return sketch_impl(c, y, p->V, p->S, p->seed, t, 0, c->smaps, nullptr);

@@ -1,7 +1,7 @@
 // Structured coil sketch (Sec. 2.3.2-2.3.3, Eqs. 11-13).
 //
 //  1. Coil covariance R = sum_i k_i k_i^H of the raw samples k_i = y_i / sqrt(w_i)
-//     (PCA coil compression, Alg. 1 line 4 / Sec. 3.1), accumulated in FP64:
+//     (PCA coil compression, Alg. 1 and Sec. 3.1), accumulated in FP64:
 //     each block sums a fixed range of samples, then the block partials are
 //     summed in index order.
 //  2. R = U diag(lambda) U^H by cyclic complex Jacobi rotations in FP64 in one
