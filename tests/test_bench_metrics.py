@@ -55,3 +55,11 @@ def test_byte_models_of_the_normal_apply():
     want = C * per_coil + 2 * 8 * n * n + 12 * N2
     assert bench.model_bytes_normal_2d(n, n, m, m, N2, C) == want
     assert bench.min_bytes_normal(n * n, N2, 2, C) == 8 * n * n * (2 + 2 * C) + 12 * N2
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2 and "one GPU only" in r.stdout + r.stderr
