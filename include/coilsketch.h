@@ -213,8 +213,9 @@ typedef struct {
  *   x <- solution of (A^H A + I/tau) x = A^H y + v/tau (n_cg CG iterations
  *        warm-started at x),  xbar = 2 x_new - x_old;
  * SKETCH runs Algorithm 1 with K such PDHG iterations per subproblem, whose
- * data-consistency system is (A_S^H A_S + I/tau) x = A_S^H A_S x^t - d^t + v/tau.  CS_RECON_SKETCH_LEARNED runs
- * Algorithm 1 with each subproblem's FISTA started at
+ * data-consistency system is (A_S^H A_S + I/tau) x = A_S^H A_S x^t - d^t + v/tau.
+ * CS_RECON_SKETCH_LEARNED runs Algorithm 1 with each subproblem's FISTA
+ * started at
  * z0 = x^t + s_o CNN(x^t / s_x, d^t / s_d) (s_d = rms(d^t), s_o = alpha s_d,
  * s_x = rms(x^t) or s_o while x^t = 0) when the FP64 subproblem objective
  * at z0 is no larger than at x^t, else at x^t (the fallback); the
