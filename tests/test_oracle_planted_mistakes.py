@@ -219,6 +219,28 @@ def pdhg_sketch_with_plus_d(normal_maps_fn, maps, y, dcf, b, x0, V, S, seed, T, 
     return x, st
 
 
+def covariance_of_weighted_samples(y, dcf=None):
+    # the density weights are not divided out
+    k = np.asarray(y, dtype=np.complex128)
+    return k.T @ np.conj(k)
+
+
+def pad_uncentred(self, z):
+    # image index i placed at grid index i instead of (i - n/2) mod m
+    C = z.shape[-1]
+    g = np.zeros(self.gshape + (C,), dtype=np.complex128)
+    g[tuple(slice(0, n) for n in self.shape)] = z
+    return g
+
+
+def kb_ft_with_sin_for_sinh(nu, W, beta):
+    nu = np.asarray(nu, dtype=np.float64)
+    a = beta ** 2 - (math.pi * W * nu) ** 2
+    s = np.sqrt(np.abs(a))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return np.where(a != 0, W * np.sin(s) / s, W)
+
+
 def conv3d_mirrored_taps(x, W, b):
     # tap (dz, dy, dx) reads the mirrored offset: a correlation turned into a
     # convolution
@@ -286,6 +308,12 @@ CASES = [
      [p_l2.test_sketch_with_all_coils_is_one_newton_step]),
     ("TV subproblem with +d", tv, "pdhg_sketch", pdhg_sketch_with_plus_d,
      [p_tv.test_sketch_with_all_coils_matches_the_plain_solver]),
+    ("covariance of the weighted samples", sketch, "covariance",
+     covariance_of_weighted_samples, [p_sketch.test_covariance_undoes_the_density_weights]),
+    ("zero padding without centring", nufft.Plan, "_pad", pad_uncentred,
+     [p_nufft.test_against_brute_force_ndft_2d_and_3d]),
+    ("KB transform with sin for sinh", nufft, "kb_ft", kb_ft_with_sin_for_sinh,
+     [p_nufft.test_kb_fourier_transform_by_quadrature]),
     ("convolution with mirrored taps", cnn, "conv3d", conv3d_mirrored_taps,
      [p_cnn.test_delta_kernel_is_identity_and_shift, p_cnn.test_conv_matches_brute_force_sum]),
 ]

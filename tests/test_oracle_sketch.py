@@ -76,6 +76,23 @@ def test_virtual_maps_and_virtual_data_describe_one_measurement():
     assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(b))
 
 
+def test_covariance_undoes_the_density_weights():
+    # y = w^1/2 * k: the covariance is that of the raw samples k, and samples
+    # with w = 0 (which carry no information about k) are left out
+    shape = (16, 16)
+    maps = synth.coil_maps(shape, 4, 51)
+    x = synth.phantom(shape, 52)
+    coords = synth.radial_traj(16, 8)
+    w = synth.radial_dcf(coords, 16).copy()
+    w[::7] = 0.0
+    k = nufft.Plan(shape, coords, None).forward(x, maps)
+    y = nufft.Plan(shape, coords, w).forward(x, maps)
+    keep = w > 0
+    ref = k[keep].T @ np.conj(k[keep])
+    R = sk.covariance(y, w)
+    assert np.max(np.abs(R - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
 def test_rotation_invariance_cartesian_and_nufft():
     shape, x, maps, mask, y = _problem(5)
     lam, U = sk.pca(sk.covariance(y))
