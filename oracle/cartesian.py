@@ -1,4 +1,5 @@
-"""Cartesian multi-coil SENSE operator (oracle, float64).
+"""Cartesian multi-coil SENSE operator (oracle, float64; test infrastructure:
+only tests, the smoke check and the benchmark's CPU baseline use it).
 
 Sec. 2.1, Eq. 2: k = F C x with F = I_C (x) F~ and, for Cartesian imaging,
 F~ = U F~_u: the unitary DFT followed by a 0/1 undersampling.  Following the

@@ -1,4 +1,6 @@
-"""Non-Cartesian multi-coil SENSE operator with a Kaiser-Bessel NUFFT (oracle).
+"""Non-Cartesian multi-coil SENSE operator with a Kaiser-Bessel NUFFT (oracle,
+float64; test infrastructure: only tests, the smoke check and the
+benchmark's CPU baseline use it).
 
 Sec. 2.1, Eq. 1 defines the forward model as the non-uniform DFT
 

@@ -1,4 +1,5 @@
-"""Reconstruction solvers (oracle, float64).
+"""Reconstruction solvers (oracle, float64; test infrastructure: only tests,
+the smoke check and the benchmark's CPU baseline use it).
 
 * ``fista_full``   -- FISTA (Beck & Teboulle) on the full problem
                       min 1/2 ||A x - y||^2 + lambda ||Psi x||_1 (Eqs. 3-4,

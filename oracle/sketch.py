@@ -1,4 +1,6 @@
-"""PCA virtual coils and the structured coil sketch (oracle, float64).
+"""PCA virtual coils and the structured coil sketch (oracle, float64; test
+infrastructure: only tests, the smoke check and the benchmark's CPU baseline
+use it).
 
 Sec. 2.3.2 (Eqs. 11-13): the sketch S^t = S~^t (x) I_N mixes coils only, so
 A_S^t = W^1/2 F C_S^t with sketched maps c^[d] = S~^t c[d] at every pixel d.

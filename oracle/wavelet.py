@@ -1,4 +1,6 @@
-"""Unitary periodized Daubechies-4 wavelet transform and the l1 prox (oracle).
+"""Unitary periodized Daubechies-4 wavelet transform and the l1 prox (oracle,
+float64; test infrastructure: only tests, the smoke check and the
+benchmark's CPU baseline use it).
 
 Sec. 2.1 lists g(x) = lambda ||Psi x||_1 with Psi a unitary wavelet transform;
 Sec. 3.3.1 names the Daubechies 4 wavelet.
