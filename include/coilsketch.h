@@ -251,7 +251,9 @@ int cs_cnn_train_step(cs_cnn* n, const float* in, const float* target, int nz, i
 /* Training pairs from the sketched solver itself: runs T outer iterations of
  * Algorithm 1 (mode CS_RECON_SKETCH parameters) from x_inout and writes, for
  * outer iteration t, the packed input at inputs + t D 4 and the target
- * (x^{t+1} - x^t) / s_o at targets + t D 2 (device FP32).  Synchronous. */
+ * (x^{t+1} - x^t) / s_o at targets + t D 2 (device FP32).  l1-wavelet on
+ * all coils only: CS_EINVAL for another regularizer, for 0 < C0 < C and for
+ * init_iters != 0.  Synchronous. */
 int cs_cnn_collect(cs_ctx* ctx, const void* y, const cs_recon_params* p, void* x_inout,
                    float* inputs, float* targets);
 
@@ -285,8 +287,9 @@ const char* cs_batch_last_error(const cs_batch* b);
 
 /* Algorithm 1 on every slice: y[i] device [N_i][C_i] (host array of device
  * pointers), p[i] host params (mode CS_RECON_SKETCH, one T and K for all;
- * lam, V, S, seed, t0, step, n_pow per slice; x_ref and reuse_b ignored),
- * x[i] device [D_i] in/out.  use_graph = 0 issues the inner iterations
+ * lam, V, S, seed, t0, step, n_pow per slice; x_ref and reuse_b ignored;
+ * l1-wavelet on all coils: CS_EINVAL for another regularizer, for
+ * 0 < C0 < C_i and for init_iters != 0), x[i] device [D_i] in/out.  use_graph = 0 issues the inner iterations
  * eagerly (the reference for the graph path: same kernels, same results).
  * st: host array of n (may be NULL).  Synchronous: waits for earlier work on
  * the slice streams first and for all of its own work before returning. */

@@ -877,6 +877,10 @@ int cs_cnn_collect(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_
   if (!y_ || !p || !x_inout || !inputs || !targets) return fail(c, CS_EINVAL, "null argument");
   if (p->T < 1 || p->K < 1) return fail(c, CS_EINVAL, "iteration counts");
   if (p->reg != CS_REG_L1WAV) return fail(c, CS_EINVAL, "pairs are collected for l1-wavelet only");
+  if ((p->C0 > 0 && p->C0 < c->C) || p->init_iters != 0)
+    return fail(c, CS_EINVAL,
+                "pairs are collected on all coils, without compression or the "
+                "classical-sketch initialisation");
   const float2* y = (const float2*)y_;
   float2* x = (float2*)x_inout;
   const long long D = c->D;
@@ -887,6 +891,7 @@ int cs_cnn_collect(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_
   const int Ch = p->V + p->S;
   CS_TRY(adjoint_all(c, c->maps, c->C, y, b));
   c->have_b = true;
+  c->b_c0 = c->C;  // b is over every coil: a compressed recon_run must not reuse it
   CS_TRY(sketch_impl(c, y, p->V, p->S, p->seed, p->t0, 0, c->smaps, nullptr));
   double alpha = p->step;
   if (alpha <= 0) {
