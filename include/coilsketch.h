@@ -201,7 +201,9 @@ typedef struct {
 
 /* Reconstruction (Algorithm 1 or the plain solver) of x from data y on the
  * operator bound by cs_set_operator.  y device [N][C]; x_inout device [D]:
- * x^{t0} on entry, the result on exit.  With CS_REG_L2, FULL runs T CG
+ * x^{t0} on entry, the result on exit.  The PCA basis comes from the data of
+ * the first sketch after cs_set_operator and stays cached for later calls
+ * (sketch_build with refresh recomputes it from new data).  With CS_REG_L2, FULL runs T CG
  * iterations on (A^H A + lambda I) x = A^H y from x^{t0}, and SKETCH runs
  * Algorithm 1 whose subproblem (Eq. 10 with g = lambda/2 ||x||^2) is the
  * linear system (A_S^H A_S + lambda I) u = -(d^t + lambda x^t), solved by K
