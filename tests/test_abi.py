@@ -81,3 +81,17 @@ def test_every_entry_point_rejects_null_handles_without_gpu():
             assert isinstance(r, bytes), name
         elif f.restype is None:
             assert r is None, name
+
+
+def test_binding_refuses_host_tensors_and_wrong_dtypes():
+    # the binding only marshals device pointers: a host tensor is an error,
+    # never a CPU code path
+    import torch
+    from paper_2305_06482_amd import binding
+    x = torch.zeros(4, 4, dtype=torch.complex64)
+    with pytest.raises(ValueError, match="device tensor"):
+        binding._need(x, torch.complex64, (4, 4), "x")
+    with pytest.raises(TypeError, match="complex64"):
+        binding._need(x.to(torch.complex128), torch.complex64, (4, 4), "x")
+    with pytest.raises(TypeError, match="torch tensor"):
+        binding._need(x.numpy(), torch.complex64, (4, 4), "x")
