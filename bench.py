@@ -31,12 +31,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per spreading launch (spread kernel + merge of its partial tiles)
-# over the timed mix of 12- and 16-coil launches on the full cones workload,
-# from FETCH_SIZE (x 2.00) and WRITE_SIZE (x 1.00) counter runs calibrated on
-# the plain copy kernel; to be re-measured (or set to None) when those kernels
-# change.
-SPREAD_TRAFFIC_BYTES = 10.94e9
 METRIC = ("normal_apply GB/s & %roofline; time-to-1e-3 NRMSE sketched+learned vs "
           "full-coil")
 
@@ -87,6 +81,9 @@ def hbm_copy_bandwidth(nbytes=2 << 30, reps=10):
     return {"bytes_per_copy": 2 * nbytes, "ms": ms, "GB/s": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
+KERNEL_LAUNCHES_PER_APPLY = {"fft_pass": 6}
+
+
 def kernel_bytes(geom, cb):
     """Algorithmic bytes per launch of the main kernels for a coil chunk cb."""
     nz, ny, nx, mz, my, mx, N = geom
@@ -97,26 +94,73 @@ def kernel_bytes(geom, cb):
     return {"fft_pass": passes / 6.0, "interp": interp, "spread": spread}
 
 
-def cpu_baseline(p, Ch, geom):
-    """The FP64 oracle's normal apply for one coil at full size, scaled to the
-    Ch coils of a sketched apply."""
+def _oracle_coil_worker(tmpdir, coils, barrier, queue):
+    """One process of the CPU baseline: the oracle's normal apply for the
+    given coils of the sketched map set, single-threaded, timed from a
+    barrier shared by all workers (the plan is built before it)."""
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = "1"
     import numpy as np
+    sys.path.insert(0, ROOT)
     from oracle import nufft
-    coords = p.coords.astype(np.float32).astype(np.float64)
-    dcf = p.dcf.astype(np.float32).astype(np.float64)
-    plan = nufft.Plan(p.shape, coords, dcf)
-    m1 = p.maps[..., :1]
-    x = p.x_true
-    t0 = time.perf_counter()
-    ref = plan.normal(x, m1)
-    dt = time.perf_counter() - t0
-    per_apply = dt * Ch
-    gbs = model_bytes_normal(geom, Ch) / per_apply / 1e9
-    return {"value": gbs, "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": (f"one coil of the sketched normal apply at full size "
-                       f"({p.shape[0]}x{p.shape[1]}x{p.shape[2]}, {coords.shape[0]} samples), "
-                       f"{dt:.1f} s, scaled x{Ch}; NumPy FFT and bincount are single-threaded"),
-            "seconds_per_apply": per_apply}, ref
+    coords = np.load(os.path.join(tmpdir, "coords.npy")).astype(np.float64)
+    dcf = np.load(os.path.join(tmpdir, "dcf.npy")).astype(np.float64)
+    x = np.load(os.path.join(tmpdir, "x.npy")).astype(np.complex128)
+    maps = np.load(os.path.join(tmpdir, "maps.npy"), mmap_mode="r")
+    shape = x.shape
+    plan = nufft.Plan(shape, coords, dcf)
+    mine = [np.ascontiguousarray(maps[..., c:c + 1]).astype(np.complex128) for c in coils]
+    barrier.wait()
+    t0 = time.time()
+    outs = [plan.normal(x, m) for m in mine]
+    t1 = time.time()
+    queue.put((coils, t0, t1, outs[0] if 0 in coils else None))
+
+
+def cpu_baseline(p, Ch, geom, max_workers=16):
+    """The FP64 oracle, as it stands, on one complete sketched normal apply at
+    full size: the Ch coils are independent, so each runs in its own
+    single-threaded worker process (NumPy's FFT and bincount are
+    single-threaded) on up to min(Ch, cores, max_workers) host cores.  The
+    time is the span from the common start barrier to the last worker's end.
+    Returns the baseline record and the oracle's result for the first coil
+    (the FP64 reference of the precision report)."""
+    import multiprocessing as mp
+    import shutil
+    import tempfile
+    import numpy as np
+    workers = max(1, min(Ch, os.cpu_count() or 1, max_workers))
+    groups = [list(range(w, Ch, workers)) for w in range(workers)]
+    tmp = tempfile.mkdtemp(prefix="cs_cpu_baseline_")
+    try:
+        np.save(os.path.join(tmp, "coords.npy"), p.coords.astype(np.float32))
+        np.save(os.path.join(tmp, "dcf.npy"), p.dcf.astype(np.float32))
+        np.save(os.path.join(tmp, "x.npy"), p.x_true.astype(np.complex64))
+        # stand-in for the Ch sketched maps: the first Ch coil maps (the cost
+        # does not depend on the values)
+        np.save(os.path.join(tmp, "maps.npy"),
+                np.ascontiguousarray(p.maps[..., :Ch]).astype(np.complex64))
+        ctx = mp.get_context("spawn")
+        barrier, queue = ctx.Barrier(workers), ctx.Queue()
+        procs = [ctx.Process(target=_oracle_coil_worker, args=(tmp, g, barrier, queue))
+                 for g in groups]
+        for pr in procs:
+            pr.start()
+        res = [queue.get() for _ in procs]
+        for pr in procs:
+            pr.join()
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    t0 = min(r[1] for r in res)
+    t1 = max(r[2] for r in res)
+    ref = next(r[3] for r in res if r[3] is not None)
+    secs = t1 - t0
+    gbs = model_bytes_normal(geom, Ch) / secs / 1e9
+    return {"value": round(gbs, 4), "unit": "GB/s", "cores": workers, "kind": "oracle",
+            "sample": (f"one {Ch}-coil sketched normal apply at full size "
+                       f"({p.shape[0]}x{p.shape[1]}x{p.shape[2]}, {p.coords.shape[0]} "
+                       f"samples), one coil per single-threaded worker, {secs:.1f} s"),
+            "seconds_per_apply": round(secs, 2)}, ref
 
 
 TTA_THRESHOLDS = (5e-2, 1e-2, 1e-3)
@@ -692,14 +736,93 @@ def precision_report(ctx, p, Ch, cpu_ref, log):
     return out
 
 
+HEADLINE_MAX_CHARS = 4000
+# kernel kind (library timer) -> the source file that holds it; a counter
+# summary in profiles/ is used for `roofline.traffic` only while the hash of
+# that file and of the internal header still match the ones it was taken with
+KIND_SOURCES = {"fft_pass": "fft_pass.hip", "interp": "grid.hip", "spread": "grid.hip",
+                "grid_normal": "grid.hip", "spread_merge": "grid.hip"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_cones3d.md")
+
+
+def kernel_source_hash(kind):
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2305_06482_amd", "csrc")
+    h = hashlib.sha256()
+    for f in (KIND_SOURCES.get(kind, ""), "cs_internal.h"):
+        path = os.path.join(csrc, f)
+        if not f or not os.path.exists(path):
+            return None
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kind, path=TRAFFIC_FILE):
+    """HBM bytes per launch of kernel kind from the committed counter summary
+    (lines `traffic <kind> <bytes per launch> <source hash>`), or None when
+    there is none or the kernel's source changed since it was taken."""
+    if not os.path.exists(path):
+        return None
+    want = kernel_source_hash(kind)
+    with open(path) as fh:
+        for line in fh:
+            f = line.strip().strip("`").split()
+            if len(f) == 4 and f[0] == "traffic" and f[1] == kind and f[3] == want:
+                return float(f[2])
+    return None
+
+
+def headline(out):
+    """The one-line JSON record: the headline metric, the dominant kernel's
+    roofline, the CPU baseline and the precision against FP64; the rest of
+    the run goes to the detail file."""
+    keys = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+            "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config",
+            "pct_hbm_roofline", "normal_apply_ms", "min_GBs", "hbm_copy_GBs", "roofline",
+            "cpu_baseline", "precision", "time_to_1e-3", "detail_file")
+    h = {k: out[k] for k in keys if k in out}
+    s = json.dumps(h, separators=(",", ":"))
+    if len(s) > HEADLINE_MAX_CHARS:
+        raise ValueError(f"headline line is {len(s)} characters")
+    return s
+
+
+def kernel_table(prof, geom, Ch, n_sk, n_full, C):
+    """Per kernel kind: total ms, launches, and the algorithmic bytes of its
+    launches in the profiled steps (sketched applies with Ch coils, full
+    applies in chunks of 16)."""
+    kb_sk = kernel_bytes(geom, Ch)
+    chunks = [16] * (C // 16) + ([C % 16] if C % 16 else [])
+    kern = {}
+    for name, (ms, cnt) in prof.items():
+        entry = {"ms": ms, "launches": cnt}
+        if name in kb_sk and cnt:
+            per = KERNEL_LAUNCHES_PER_APPLY.get(name, 1)
+            tot = kb_sk[name] * per * n_sk
+            tot += sum(kernel_bytes(geom, cb)[name] * per for cb in chunks) * n_full
+            entry["algorithmic_GB"] = tot / 1e9
+            entry["GB/s"] = tot / (ms * 1e-3) / 1e9
+            entry["bytes_per_launch"] = tot / cnt
+        kern[name] = entry
+    return kern
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--K", type=int, default=5)
+    ap.add_argument("--profile-steps", type=int, default=3,
+                    help="extra steps run with per-kernel HIP events for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--small", action="store_true", help="48^3 instance (quick check)")
+    ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="file for the full record and the secondary studies")
+    ap.add_argument("--studies", action="store_true",
+                    help="also run the secondary studies (time to accuracy, batched slices, "
+                         "l1-TV, sketch designs, g-factor) into the detail file")
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-accuracy runs")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-slice batch")
     ap.add_argument("--no-tv", action="store_true",
@@ -757,7 +880,8 @@ def main():
     dcf = dt(p.dcf, torch.float32)
     t0 = time.time()
     ctx.set_operator(maps, coords=coords, dcf=dcf)
-    log(f"operator set (trajectory sorted and binned) in {time.time() - t0:.1f} s")
+    setup_s = time.time() - t0
+    log(f"operator set (trajectory sorted and binned) in {setup_s:.2f} s")
     torch.cuda.synchronize()
     # device memory held by the context and its inputs (the library allocates
     # with hipMalloc, outside torch's pool): every coil stays resident
@@ -782,36 +906,44 @@ def main():
 
     x = torch.zeros(p.shape, dtype=torch.complex64, device=dev)
     t_idx = 1
-    for _ in range(args.warmup):
-        ctx.recon_run(y, mode="sketch", lam=p.lam, T=1, K=args.K, V=V, S=S, seed=p.seed,
-                      t0=t_idx, step=alpha, reuse_b=True, x=x)
+
+    def step():
+        nonlocal t_idx
+        r = ctx.recon_run(y, mode="sketch", lam=p.lam, T=1, K=args.K, V=V, S=S, seed=p.seed,
+                          t0=t_idx, step=alpha, reuse_b=True, x=x)
         t_idx += 1
+        return r
+
+    for _ in range(args.warmup):
+        step()
     torch.cuda.synchronize()
     log("warmup done")
 
-    ctx.profile_enable(True)
-    ctx.profile_read()
+    # timed region: per-kernel events off; the phase events of recon_run
+    # (a few per outer iteration) give the applies' GPU time
+    ctx.profile_enable(False)
     results = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        r = ctx.recon_run(y, mode="sketch", lam=p.lam, T=1, K=args.K, V=V, S=S, seed=p.seed,
-                          t0=t_idx, step=alpha, reuse_b=True, x=x)
-        results.append(r)
-        t_idx += 1
+        results.append(step())
     torch.cuda.synchronize()
     t_end = time.perf_counter()
-    prof = ctx.profile_read()
-    ctx.profile_enable(False)
     ms_per_step = (t_end - t_start) * 1e3 / args.steps
     log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step")
+
+    # profiled pass: the same steps with a HIP event pair around every kernel
+    # launch on the context stream (the roofline's per-launch durations)
+    ctx.profile_enable(True)
+    ctx.profile_read()
+    presults = [step() for _ in range(max(1, args.profile_steps))]
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
 
     n_sk = sum(r.n_sketch_applies for r in results)
     n_full = sum(r.n_full_applies for r in results)
     ms_sk = sum(r.ms_sketch_normal for r in results)
     ms_full = sum(r.ms_full_normal for r in results)
-    ms_prox = sum(r.ms_prox for r in results)
-    ms_sketch = sum(r.ms_sketch for r in results)
     b_sk = model_bytes_normal(geom, Ch)
     b_full = model_bytes_normal(geom, C)
     D3 = nz * ny * nx
@@ -820,34 +952,18 @@ def main():
     gbs = b_sk * n_sk / (ms_sk * 1e-3) / 1e9
     gbs_full = b_full * n_full / (ms_full * 1e-3) / 1e9
 
-    # dominant kernel and its roofline
-    kb_sk = kernel_bytes(geom, Ch)
-    kb_full = kernel_bytes(geom, 16)
-    kern = {}
-    # the gridding step is the spread kernel plus the merge of its partial
-    # tiles: its algorithmic bytes are charged to the pair
-    merge_ms = prof.get("spread_merge", (0.0, 0))[0]
-    for name, (ms, cnt) in prof.items():
-        if name == "spread":
-            ms = ms + merge_ms
-        entry = {"ms": ms, "launches": cnt}
-        if name in kb_sk and cnt:
-            per_sk = 6 if name == "fft_pass" else 1
-            tot = (kb_sk[name] * per_sk * n_sk + kb_full[name] * per_sk * 2 * n_full)
-            entry["algorithmic_GB"] = tot / 1e9
-            entry["GB/s"] = tot / (ms * 1e-3) / 1e9
-            entry["bytes_per_launch"] = tot / cnt
-        kern[name] = entry
+    kern = kernel_table(prof, geom, Ch, sum(r.n_sketch_applies for r in presults),
+                        sum(r.n_full_applies for r in presults), C)
     dom = max(kern, key=lambda k: kern[k]["ms"])
     roof = None
     if "GB/s" in kern[dom]:
         ach = kern[dom]["GB/s"]
+        tr = None if args.small else measured_traffic(dom)
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                "avg_launch_ms": kern[dom]["ms"] / kern[dom]["launches"],
-                "bytes_per_launch": kern[dom]["bytes_per_launch"],
-                "traffic": (SPREAD_TRAFFIC_BYTES if dom == "spread" and not args.small
-                            else None)}
+                "traffic": tr,
+                "avg_launch_ms": round(kern[dom]["ms"] / kern[dom]["launches"], 4),
+                "bytes_per_launch": round(kern[dom]["bytes_per_launch"])}
 
     out = {
         "metric": METRIC,
@@ -864,29 +980,49 @@ def main():
         "data": "synthetic",
         "config": {"workload": ("cones3d_48x48x48" if args.small else "cones3d_192x192x128")
                    + f"_N{geom[6]}_C{C}_sketch{V}+{S}_K{args.K}",
-                   "grid": [mz, my, mx], "samples_per_coil": geom[6], "coils": C,
-                   "sketched_coils": Ch},
+                   "grid": [mz, my, mx]},
         "pct_hbm_roofline": round(100 * gbs / HBM_PEAK_GBS, 2),
-        "normal_apply_ms": {"sketched": ms_sk / max(1, n_sk), "full": ms_full / max(1, n_full)},
+        "normal_apply_ms": {"sketched": round(ms_sk / max(1, n_sk), 3),
+                            "full": round(ms_full / max(1, n_full), 3)},
         "full_normal_GBs": round(gbs_full, 1),
-        "phase_ms_per_step": {"full_normal": ms_full / args.steps,
+        "phase_ms_per_step": {"full_normal": sum(r.ms_full_normal for r in results) / args.steps,
                               "sketched_normal": ms_sk / args.steps,
-                              "prox": ms_prox / args.steps, "sketch": ms_sketch / args.steps},
+                              "prox": sum(r.ms_prox for r in results) / args.steps,
+                              "sketch": sum(r.ms_sketch for r in results) / args.steps},
         "model_bytes": {"sketched": b_sk, "full": b_full},
         "min_bytes": {"sketched": bmin_sk, "full": bmin_full},
         "min_GBs": {"sketched": round(bmin_sk * n_sk / (ms_sk * 1e-3) / 1e9, 1),
                     "full": round(bmin_full * n_full / (ms_full * 1e-3) / 1e9, 1)},
+        "operator_setup_s": round(setup_s, 3),
         "device_memory": mem,
         "kernels": kern,
         "roofline": roof,
+        "detail_file": args.detail,
     }
     out["hbm_copy"] = hbm_copy_bandwidth()
+    out["hbm_copy_GBs"] = round(out["hbm_copy"]["GB/s"], 1)
     log(f"plain device copy: {out['hbm_copy']['GB/s']:.0f} GB/s")
     cpu_ref = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
         out["cpu_baseline"], cpu_ref = cpu_baseline(p, Ch, geom)
+        log(f"cpu baseline: {out['cpu_baseline']}")
     out["precision"] = precision_report(ctx, p, Ch, cpu_ref, log)
+    if args.studies:
+        run_studies(out, args, ctx, y, p, Ch, log)
+    os.makedirs(os.path.dirname(os.path.abspath(args.detail)), exist_ok=True)
+    with open(args.detail, "w") as fh:
+        json.dump(out, fh, indent=1)
+    log(f"full record written to {args.detail}")
+    ctx.close()
+    print(headline(out), flush=True)
+
+
+def run_studies(out, args, ctx, y, p, Ch, log):
+    """Secondary studies (time to accuracy, batched slices, l1-TV, sketch
+    designs, g-factor): written to the detail file only."""
+    import synth
+    V, S = p.V, p.S
     if not args.no_batched and not args.small:
         out["batched_radial"] = batched_bench(args, log)
     if not args.no_tv and not args.small:
@@ -927,8 +1063,6 @@ def main():
                 tta["cart320_seeds"] = cartesian_tta_seeds(tta["cart320"], args, log,
                                                            args.tta_cart_seeds)
         out["time_to_accuracy"] = tta
-    print(json.dumps(out), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":
