@@ -252,6 +252,30 @@ def conv3d_mirrored_taps(x, W, b):
     return out
 
 
+def objective_without_half(x, forward_fn, y, lam, levels=4):
+    r = forward_fn(x) - y
+    return float(np.vdot(r, r).real) + lam * wavelet.l1_norm(x, levels)
+
+
+def objective_with_l2_regularizer(x, forward_fn, y, lam, levels=4):
+    r = forward_fn(x) - y
+    return 0.5 * float(np.vdot(r, r).real) + lam * float(np.linalg.norm(wavelet.dwt(x, levels)))
+
+
+def objective_with_re_im_l1(x, forward_fn, y, lam, levels=4):
+    r = forward_fn(x) - y
+    c = wavelet.dwt(x, levels)
+    return 0.5 * float(np.vdot(r, r).real) + lam * float(np.sum(np.abs(c.real) + np.abs(c.imag)))
+
+
+def nrmse_squared(x, ref):
+    return float(np.linalg.norm((x - ref).ravel()) ** 2 / np.linalg.norm(ref.ravel()) ** 2)
+
+
+def nrmse_over_x(x, ref):
+    return float(np.linalg.norm((x - ref).ravel()) / np.linalg.norm(x.ravel()))
+
+
 CASES = [
     # (name, owner, attribute, planted function, pins expected to fail)
     ("cartesian forward drops the mask", cartesian, "forward", cart_forward_without_mask,
@@ -316,6 +340,15 @@ CASES = [
      [p_nufft.test_kb_fourier_transform_by_quadrature]),
     ("convolution with mirrored taps", cnn, "conv3d", conv3d_mirrored_taps,
      [p_cnn.test_delta_kernel_is_identity_and_shift, p_cnn.test_conv_matches_brute_force_sum]),
+    ("objective without the 1/2", recon, "objective", objective_without_half,
+     [p_recon.test_objective_of_wavelet_atoms_closed_form,
+      p_recon.test_objective_data_term_against_an_explicit_sum]),
+    ("objective with the l2 norm of the coefficients", recon, "objective",
+     objective_with_l2_regularizer, [p_recon.test_objective_of_wavelet_atoms_closed_form]),
+    ("objective with |re| + |im| for the modulus", recon, "objective", objective_with_re_im_l1,
+     [p_recon.test_objective_of_wavelet_atoms_closed_form]),
+    ("NRMSE of squared norms", recon, "nrmse", nrmse_squared, [p_recon.test_nrmse_hand_computed]),
+    ("NRMSE normalised by x", recon, "nrmse", nrmse_over_x, [p_recon.test_nrmse_hand_computed]),
 ]
 
 

@@ -243,3 +243,55 @@ def test_compressed_algorithm1_solves_the_compressed_problem():
     full = recon.fista_full(lambda v: nf(v, maps), af(y, maps), np.zeros(shape, complex), alpha,
                             lam, K, levels=2)
     assert np.linalg.norm(full - ref) > 1e-3 * np.linalg.norm(ref)
+
+
+def test_objective_of_wavelet_atoms_closed_form():
+    # Eqs. 3-4: 1/2 ||A x - y||^2 + lambda ||Psi x||_1.  x is a sum of two
+    # wavelet atoms, x = Psi^H (c1 e_j + c2 e_k); Psi is unitary (pinned by
+    # the wavelet tests), so ||Psi x||_1 = |c1| + |c2| (complex modulus) and
+    # ||x||^2 = |c1|^2 + |c2|^2.  With A = I: y = 0 leaves both terms, y = x
+    # only the regularizer.
+    import math
+    from oracle import wavelet
+    shape, lv, lam = (16, 16), 2, 0.25
+    c1, c2 = 3 - 4j, -1.0
+    coef = np.zeros(shape, complex)
+    coef[5, 9], coef[1, 2] = c1, c2
+    x = wavelet.idwt(coef, levels=lv)
+    ident = lambda v: v.reshape(-1)
+    l1 = abs(c1) + abs(c2)            # 6; the modulus, not |re| + |im| = 8
+    sq = abs(c1) ** 2 + abs(c2) ** 2  # 26
+    got0 = recon.objective(x, ident, np.zeros(x.size), lam, levels=lv)
+    assert math.isclose(got0, 0.5 * sq + lam * l1, rel_tol=1e-12)
+    got1 = recon.objective(x, ident, x.reshape(-1), lam, levels=lv)
+    assert math.isclose(got1, lam * l1, rel_tol=1e-12)
+
+
+def test_objective_data_term_against_an_explicit_sum():
+    # lambda = 0: the objective is half the sum over samples of |(A x - y)_i|^2
+    # for a dense complex A, written out element by element
+    g = np.random.default_rng(11)
+    shape = (4, 4)
+    A = g.standard_normal((12, 16)) + 1j * g.standard_normal((12, 16))
+    x = g.standard_normal(shape) + 1j * g.standard_normal(shape)
+    y = g.standard_normal(12) + 1j * g.standard_normal(12)
+    want = 0.0
+    for i in range(12):
+        s = sum(A[i, j] * x.reshape(-1)[j] for j in range(16)) - y[i]
+        want += s.real ** 2 + s.imag ** 2
+    want *= 0.5
+    got = recon.objective(x, lambda v: A @ v.reshape(-1), y, 0.0, levels=2)
+    assert abs(got - want) < 1e-12 * want
+
+
+def test_nrmse_hand_computed():
+    # NRMSE = ||x - ref|| / ||ref|| over all entries (Sec. 3.2.1)
+    import math
+    assert math.isclose(recon.nrmse(np.array([1.0, 3.0]), np.array([1.0, 1.0])), math.sqrt(2),
+                        rel_tol=1e-15)
+    # complex entries: ||(1j, -1)|| / ||(1, 1)|| = 1
+    assert math.isclose(recon.nrmse(np.array([1 + 1j, 0]), np.array([1.0, 1.0])), 1.0,
+                        rel_tol=1e-15)
+    # arrays of any shape are flattened: ||(3, 0, 0, 4)|| / ||(0, 0, 0, 2)|| = 5 / 2
+    assert math.isclose(recon.nrmse(np.array([[3.0, 0.0], [0.0, 6.0]]),
+                                    np.array([[0.0, 0.0], [0.0, 2.0]])), 2.5, rel_tol=1e-15)
