@@ -336,6 +336,22 @@ int cs_idwt(cs_ctx* ctx, const void* coef, void* x);
 int cs_coil_mix(cs_ctx* ctx, const void* in, int cin, const double* M, int cout,
                 void* out);
 
+/* Allocation-free coil mixing, for callers that cannot allocate (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same product as cs_coil_mix, out[d][j] = sum_c in[d][c] * M[j][c] with the
+ * same split-BF16 MFMA kernel, but with M in DEVICE memory (complex128
+ * [cout][cin] row-major, caller-owned) and its bf16 fragments packed on the
+ * GPU into a static 96 KiB scratch array of the library (one per GPU, held
+ * until the process ends), so the call makes no allocation, no host copy
+ * and no host synchronisation: two kernel launches on the context stream.
+ * in device [D][cin], out device [D][cout].  Limit: cin and cout in [1, 64]
+ * (CS_EINVAL beyond, before any device work).  Every call on a GPU shares
+ * that GPU's scratch, which keeps the last call's fragments: calls that
+ * overlap on one GPU (different streams or threads) race and must be
+ * ordered by the caller. */
+int cs_coil_mix_noalloc(cs_ctx* ctx, const void* in, int cin, const void* M, int cout,
+                        void* out);
+
 /* FP64 inner product <a, b> = sum conj(a) b of two device complex64 [D]
  * vectors; result host double[2] (re, im).  Synchronous. */
 int cs_dot(cs_ctx* ctx, const void* a, const void* b, double* out);

@@ -32,7 +32,7 @@ CS_SKETCH_RADEMACHER, CS_SKETCH_GAUSSIAN = 0, 1
 EXPORTED = [
     "cs_create", "cs_destroy", "cs_last_error", "cs_set_operator", "sense_apply",
     "sense_adjoint", "normal_apply", "sketch_build", "recon_run", "cs_prox_l1wav",
-    "cs_dwt", "cs_idwt", "cs_coil_mix", "cs_dot", "cs_power_iteration", "cs_grid_shape",
+    "cs_dwt", "cs_idwt", "cs_coil_mix", "cs_coil_mix_noalloc", "cs_dot", "cs_power_iteration", "cs_grid_shape",
     "cs_profile_enable", "cs_profile_read", "cs_batch_create", "cs_batch_destroy",
     "cs_batch_last_error", "cs_batch_recon", "cs_set_spread_cfg", "cs_autotune_spread",
     "cs_set_interp_cfg", "cs_set_sketch_dist",
@@ -146,6 +146,7 @@ def load() -> ctypes.CDLL:
     lib.cs_dwt.argtypes = [vp, vp, vp]
     lib.cs_idwt.argtypes = [vp, vp, vp]
     lib.cs_coil_mix.argtypes = [vp, vp, ci, vp, ci, vp]
+    lib.cs_coil_mix_noalloc.argtypes = [vp, vp, ci, vp, ci, vp]
     lib.cs_dot.argtypes = [vp, vp, vp, vp]
     lib.cs_power_iteration.argtypes = [vp, vp, ci, ci, vp]
     lib.cs_grid_shape.argtypes = [vp, vp]
@@ -444,6 +445,22 @@ class Context:
         self._check(self.lib.cs_coil_mix(self._ctx, _ptr(inp), cin,
                                          Mr.ctypes.data_as(ctypes.c_void_p), cout, _ptr(out)),
                     "cs_coil_mix")
+        return out
+
+    def coil_mix_noalloc(self, inp, M, out):
+        """cs_coil_mix_noalloc: M a device complex128 tensor [cout, cin]; out
+        (device complex64 image + (cout,)) is caller-allocated, as the call
+        itself allocates nothing."""
+        cin = self._maps(inp, "inp")
+        _need(M, torch.complex128, None, "M")
+        if M.dim() != 2 or int(M.shape[1]) != cin:
+            raise ValueError("M must be [cout, cin]")
+        cout = int(M.shape[0])
+        _need(out, torch.complex64, None, "out")
+        if tuple(out.shape) != self.shape + (cout,):
+            raise ValueError("out must have shape image + (cout,)")
+        self._check(self.lib.cs_coil_mix_noalloc(self._ctx, _ptr(inp), cin, _ptr(M),
+                                                 cout, _ptr(out)), "cs_coil_mix_noalloc")
         return out
 
     def dot(self, a, b):

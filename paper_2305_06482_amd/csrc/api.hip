@@ -486,7 +486,7 @@ int create_impl(const cs_geom* g, void* stream, cs_ctx** out) {
   if ((rc = upload_table(c, &c->da[0], tab[0])) || (rc = upload_table(c, &c->da[1], tab[1])) ||
       (rc = upload_table(c, &c->da[2], tab[2])) || (rc = upload_table(c, &c->dp_z, dpz)) ||
       (rc = upload_table(c, &c->dp_y, dpy)) || (rc = upload_table(c, &c->da_y1d, y1d)) ||
-      (rc = wavelet_init(c))) {
+      (rc = wavelet_init(c)) || (rc = mix_scratch_init(c))) {
     std::string e = c->err;
     cs_destroy(c);
     g_create_error = e;
@@ -803,6 +803,13 @@ int cs_idwt(cs_ctx* c, const void* coef, void* x) {
 int cs_coil_mix(cs_ctx* c, const void* in, int cin, const double* M, int cout, void* out) {
   if (!c || !in || !M || !out) return CS_EINVAL;
   return coil_mix(c, (const float2*)in, cin, 0, cin, M, cout, (float2*)out, cout, 0, 1.0f);
+}
+
+int cs_coil_mix_noalloc(cs_ctx* c, const void* in, int cin, const void* M, int cout,
+                        void* out) {
+  if (!c) return CS_EINVAL;
+  if (!in || !M || !out) return fail(c, CS_EINVAL, "null pointer");
+  return coil_mix_noalloc(c, (const float2*)in, cin, M, cout, (float2*)out);
 }
 
 int cs_dot(cs_ctx* c, const void* a, const void* b, double* out) {

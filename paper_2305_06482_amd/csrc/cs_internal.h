@@ -144,6 +144,7 @@ struct cs_ctx {
   double* cov = nullptr;          // [C][C] complex double
   double* eig_dev = nullptr;      // U and lambda from the eigensolver
   void* mixB = nullptr;           // packed bf16 B fragments for coil mixing
+  void* mix_scratch = nullptr;    // this device's static fragment scratch (no-alloc mixing)
   size_t mixB_bytes = 0;
   // pinned staging ring for the fragments' host-to-device copies; the event
   // of a slot marks its last copy, so a slot is rewritten only after it
@@ -250,6 +251,13 @@ int coil_mix(cs_ctx* c, const float2* in, int in_ldc, int in_c0, int cin,
 int coil_mix_rows(cs_ctx* c, long long rows, const float2* in, int in_ldc, int in_c0, int cin,
                   const double* M, int cout, float2* out, int out_ldc, int out_c0,
                   float out_scale);
+
+// allocation-free coil mixing (M device complex128 [cout][cin]); the
+// fragments go to a static per-device scratch whose address mix_scratch_init
+// looks up once per device
+int mix_scratch_init(cs_ctx* c);
+int coil_mix_noalloc(cs_ctx* c, const float2* in, int cin, const void* M, int cout,
+                     float2* out);
 
 // operators and solver pieces (api.hip)
 int op_normal(cs_ctx* c, const float2* maps, int ncoil, const float2* x,

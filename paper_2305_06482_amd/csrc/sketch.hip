@@ -17,6 +17,8 @@
 //     maps with them; the 1/sqrt(S) scale is applied in FP32 in the epilogue.
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "cs_internal.h"
 
@@ -315,6 +317,48 @@ __global__ __launch_bounds__(256) void k_coil_mix(const float2* __restrict__ in,
   }
 }
 
+// Packs the B fragments of k_coil_mix from a mixing matrix in device memory
+// (complex128 [cout][cin], row-major) exactly as coil_mix_rows packs them on
+// the host: real B[k][n] with k = 2 cc + (0: re, 1: im of input coil cc) and
+// n = 2 j + (0: re, 1: im of output coil j), i.e. B(2cc, 2j) = re M[j][cc],
+// B(2cc+1, 2j) = -im, B(2cc, 2j+1) = im, B(2cc+1, 2j+1) = re, split into the
+// three bf16 terms hi, mid, lo.  One thread per fragment element; every
+// element of the nK x nN blocks of all three terms is written.
+__global__ __launch_bounds__(256) void k_pack_mix(const double2* __restrict__ M, int cin,
+                                                  int cout, int nK, int nN,
+                                                  unsigned short* __restrict__ frag) {
+  const int total = nK * nN * 64 * 4;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int e = i & 3, l = (i >> 2) & 63, blk = i >> 8;
+  const int n = blk % nN, kb = blk / nN;
+  const int k = kb * 16 + 4 * (l >> 4) + e, col = n * 16 + (l & 15);
+  float v = 0.f;
+  if (k < 2 * cin && col < 2 * cout) {
+    const double2 m = M[(size_t)(col >> 1) * cin + (k >> 1)];
+    const float re = (float)m.x, im = (float)m.y;
+    v = (k & 1) == 0 ? ((col & 1) == 0 ? re : im) : ((col & 1) == 0 ? -im : re);
+  }
+  const unsigned short h = bf16_rne(v);
+  const float r1 = v - bf16_to_f(h);
+  const unsigned short mid = bf16_rne(r1);
+  const float r2 = r1 - bf16_to_f(mid);
+  const unsigned short lo = bf16_rne(r2);
+  frag[i] = h;
+  frag[total + i] = mid;
+  frag[2 * total + i] = lo;
+}
+
+// Fragment scratch of the allocation-free coil mixing: the three split terms
+// of the largest mixing matrix (64 x 64 complex: K = N = 128 real columns,
+// 8 x 8 fragment blocks of 64 lanes x 4 bf16), 96 KiB.  Each GPU that loads
+// the library holds one copy until the process ends; in host code the name
+// stands for no device address, so host code uses the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr int kMixBlocksMax = 8;
+constexpr size_t kMixFragElems = (size_t)3 * kMixBlocksMax * kMixBlocksMax * 64 * 4;
+static __device__ __align__(256) unsigned short scratch[kMixFragElems];
+
 unsigned short host_bf16(float f) {
   unsigned u;
   std::memcpy(&u, &f, 4);
@@ -430,6 +474,46 @@ int coil_mix_rows(cs_ctx* c, long long rows, const float2* in, int in_ldc, int i
   CS_KLAUNCH(c, K_MIX, k_coil_mix, dim3(nb), dim3(256), 0, c->stream, in, in_ldc, in_c0, cin,
                      rows, (const v4s*)c->mixB, nB, nK, nN, out, out_ldc, out_c0, cout,
                      out_scale);
+  CS_HIP(c, hipGetLastError());
+  return CS_OK;
+}
+
+int mix_scratch_init(cs_ctx* c) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;  // device ordinal -> address of `scratch`
+  int dev = -1;
+  CS_HIP(c, hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void* p = nullptr;
+    CS_HIP(c, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(c, CS_EHIP, "no device address for the coil-mixing scratch");
+    it = addr.emplace(dev, p).first;
+  }
+  c->mix_scratch = it->second;
+  return CS_OK;
+}
+
+int coil_mix_noalloc(cs_ctx* c, const float2* in, int cin, const void* M, int cout,
+                     float2* out) {
+  if (cin < 1 || cout < 1 || cin > kMixBlocksMax * 8 || cout > kMixBlocksMax * 8)
+    return fail(c, CS_EINVAL,
+                "cs_coil_mix_noalloc: cin and cout must be in [1, 64] (the scratch holds the "
+                "fragments of a 64 x 64 mixing matrix at most)");
+  if (!c->mix_scratch) return fail(c, CS_EHIP, "coil-mixing scratch address not set up");
+  const int nK = (2 * cin + 15) / 16, nN = (2 * cout + 15) / 16;
+  const int total = nK * nN * 64 * 4;
+  auto* frag = (unsigned short*)c->mix_scratch;
+  CS_KLAUNCH(c, K_MIX, k_pack_mix, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+             c->stream, (const double2*)M, cin, cout, nK, nN, frag);
+  CS_HIP(c, hipGetLastError());
+  const long long rows = c->D;
+  if (rows <= 0) return CS_OK;
+  const long long tiles = (rows + 15) / 16;
+  const unsigned nb = (unsigned)((tiles + 3) / 4);
+  CS_KLAUNCH(c, K_MIX, k_coil_mix, dim3(nb), dim3(256), 0, c->stream, in, cin, 0, cin, rows,
+             (const v4s*)frag, 3, nK, nN, out, cout, 0, cout, 1.0f);
   CS_HIP(c, hipGetLastError());
   return CS_OK;
 }
