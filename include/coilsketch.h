@@ -27,8 +27,13 @@
  *    error), CS_ENUMERIC (-4: NaN or divergence).  cs_last_error() gives a
  *    message.  No exception crosses the ABI.
  *  - A context is bound to one stream and is not thread-safe.  It allocates
- *    its working memory in cs_create()/cs_set_operator() and frees it in
- *    cs_destroy(); operator calls allocate nothing.
+ *    its working memory in cs_create() (or takes it from the caller's
+ *    workspace, cs_create_ws) and cs_set_operator(), and frees it in
+ *    cs_destroy().  sense_apply, sense_adjoint, normal_apply, sketch_build,
+ *    the building blocks and recon_run's default path allocate nothing; the
+ *    exceptions are named where they apply (recon_run's initial compression
+ *    and classical-sketch initialisation buffers, and the CNN's activations,
+ *    on first use, unless cs_reserve_recon made them).
  */
 #ifndef COILSKETCH_H
 #define COILSKETCH_H
@@ -68,6 +73,22 @@ typedef struct {
 /* Create a context for geometry g on HIP stream `stream` (a hipStream_t, or
  * NULL for the default stream).  On success *out holds the context. */
 int cs_create(const cs_geom* g, void* stream, cs_ctx** out);
+
+/* Device bytes of the work buffers a context for geometry g needs (grids of
+ * the FFT passes, sample values, images, reductions, sketch and wavelet
+ * buffers), for a caller who provides them through cs_create_ws.  Validates
+ * g as cs_create does; no device work. */
+int cs_workspace_size(const cs_geom* g, size_t* bytes);
+
+/* cs_create with a caller-owned workspace: `workspace` is device memory of at
+ * least cs_workspace_size(g) bytes at a 256-byte boundary (a torch buffer,
+ * say) that must stay valid until cs_destroy, which does not free it
+ * (CS_EINVAL if it is smaller or misaligned).  The small per-axis tables, the
+ * FFT twiddles and the coil-mixing fragment buffers are still allocated
+ * here, and cs_set_operator still allocates the trajectory's sorted records,
+ * work items and partial tiles (their sizes depend on the binning). */
+int cs_create_ws(const cs_geom* g, void* workspace, size_t ws_bytes, void* stream,
+                 cs_ctx** out);
 
 /* Destroy a context and free its device memory (synchronises its stream). */
 void cs_destroy(cs_ctx* ctx);
@@ -122,6 +143,23 @@ int normal_apply(cs_ctx* ctx, const void* maps, int ncoil, const void* x, void* 
 int sketch_build(cs_ctx* ctx, const void* y, int V, int S, uint64_t seed, int t,
                  int refresh, void* smaps, double* eig, double* U_out,
                  int8_t* signs);
+
+/* Inject the PCA basis instead of computing it from the data (Sec. 2.3.3
+ * fixes U only up to the phase of each eigenvector): U host complex128
+ * [C][C] row-major with column j the eigenvector of virtual coil j
+ * (c'_j = sum_c conj(U[c][j]) c_c), lam host [C] float64 or NULL.  Forms and
+ * caches the virtual maps (asynchronous); later sketch_build and recon_run
+ * calls use them until cs_set_operator or a sketch_build with refresh. */
+int cs_set_basis(cs_ctx* ctx, const double* U, const double* lam);
+
+/* Inject the random block of the sketching matrix (Eq. 11, S~_S): R host
+ * float64 [S][C - V] row-major, taken as given (any 1/sqrt(S) scale
+ * included), so the sketched coils are c^_{V+a} = sum_b R[a][b] c'_{V+b}.
+ * Every later sketch_build and recon_run with this V and S on all C coils
+ * uses it at every outer iteration instead of the seeded draw (and reports
+ * no signs); R = NULL returns to the draw.  Requires V >= 0, S >= 1,
+ * V + S <= C, V < C. */
+int cs_set_sketch(cs_ctx* ctx, int V, int S, const double* R);
 
 /* Distribution of the random block (Sec. 3.2): Rademacher (the default) or
  * Gaussian with variance 1/S (values / sqrt(S) with unit-variance values;
@@ -198,6 +236,13 @@ typedef struct {
   long long n_warm_accepted, n_warm_rejected;
   double ms_warm;
 } cs_recon_stats;
+
+/* Allocate recon_run's optional buffers now, so that recon_run allocates
+ * nothing: the compressed maps and data of an initial compression to up to
+ * C0 virtual coils ([D][C0] and [N][C0]) and the sketched data of the
+ * classical-sketch initialisation with up to init_coils = V + S coils
+ * ([N][init_coils]); 0 skips either.  Synchronous (hipMalloc). */
+int cs_reserve_recon(cs_ctx* ctx, int C0, int init_coils);
 
 /* Reconstruction (Algorithm 1 or the plain solver) of x from data y on the
  * operator bound by cs_set_operator.  y device [N][C]; x_inout device [D]:
@@ -299,9 +344,14 @@ int cs_batch_recon(cs_batch* b, const void* const* y, const cs_recon_params* p,
                    void* const* x, int use_graph, cs_batch_stats* st);
 
 /* ---- spreading work-group shapes and their autotuner --------------------- */
-#define CS_SPREAD_NCFG 7
+#define CS_SPREAD_NCFG 8
 /* Select spreading shape cfg in [0, CS_SPREAD_NCFG) for this context (all
- * shapes give bit-identical results; they differ only in speed). */
+ * shapes give bit-identical results; they differ only in speed).  Shape 0,
+ * the default, keeps the sample values of the 3D normal operator in vector
+ * registers and broadcasts them with v_readlane; shape 7 stages them in LDS
+ * (as every shape does for 2D and for the adjoint's caller data); 1-6 vary
+ * the waves and coils per work-group.  CS_SPREAD_CFG in the environment
+ * sets the default of new operators. */
 int cs_set_spread_cfg(cs_ctx* ctx, int cfg);
 /* Time a normal apply with the given maps (device [D][ncoil]) under every
  * shape (reps applies each, HIP events on the context stream), select the

@@ -30,17 +30,18 @@ CS_REG_L1WAV, CS_REG_L2, CS_REG_TV = 0, 1, 2
 CS_SKETCH_RADEMACHER, CS_SKETCH_GAUSSIAN = 0, 1
 
 EXPORTED = [
-    "cs_create", "cs_destroy", "cs_last_error", "cs_set_operator", "sense_apply",
+    "cs_create", "cs_create_ws", "cs_workspace_size", "cs_destroy", "cs_last_error", "cs_set_operator", "sense_apply",
     "sense_adjoint", "normal_apply", "sketch_build", "recon_run", "cs_prox_l1wav",
     "cs_dwt", "cs_idwt", "cs_coil_mix", "cs_coil_mix_noalloc", "cs_dot", "cs_power_iteration", "cs_grid_shape",
     "cs_profile_enable", "cs_profile_read", "cs_batch_create", "cs_batch_destroy",
     "cs_batch_last_error", "cs_batch_recon", "cs_set_spread_cfg", "cs_autotune_spread",
-    "cs_set_interp_cfg", "cs_set_sketch_dist",
+    "cs_set_interp_cfg", "cs_set_sketch_dist", "cs_set_basis", "cs_set_sketch",
+    "cs_reserve_recon",
     "cs_cnn_create", "cs_cnn_destroy", "cs_cnn_last_error", "cs_cnn_num_params",
     "cs_cnn_get_params", "cs_cnn_set_params", "cs_cnn_forward", "cs_cnn_loss_grad",
     "cs_cnn_train_step", "cs_cnn_collect",
 ]
-SPREAD_NCFG = 7
+SPREAD_NCFG = 8
 INTERP_NCFG = 4
 NKERNELS = 12
 KERNEL_KINDS = ["fft_pass", "interp", "spread", "gather", "wavelet", "soft", "vec", "reduce",
@@ -132,6 +133,12 @@ def load() -> ctypes.CDLL:
     lib = ctypes.CDLL(LIB_PATH)
     vp, ci, cf, cd = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_double
     lib.cs_create.argtypes = [ctypes.POINTER(Geom), vp, ctypes.POINTER(vp)]
+    lib.cs_create_ws.argtypes = [ctypes.POINTER(Geom), vp, ctypes.c_size_t, vp,
+                                 ctypes.POINTER(vp)]
+    lib.cs_workspace_size.argtypes = [ctypes.POINTER(Geom), ctypes.POINTER(ctypes.c_size_t)]
+    lib.cs_set_basis.argtypes = [vp, vp, vp]
+    lib.cs_set_sketch.argtypes = [vp, ci, ci, vp]
+    lib.cs_reserve_recon.argtypes = [vp, ci, ci]
     lib.cs_destroy.argtypes = [vp]
     lib.cs_destroy.restype = None
     lib.cs_last_error.argtypes = [vp]
@@ -223,11 +230,40 @@ class ReconResult:
     dist: list = field(default_factory=list)
 
 
+def _geom(shape, ncoil, kind="cart", nsamp=0, sigma=1.25, kwidth=4, beta=0.0, wav_levels=4):
+    g = Geom()
+    g.ndim = len(shape)
+    for i, s in enumerate(shape):
+        g.n[i] = int(s)
+    g.ncoil = int(ncoil)
+    g.kind = CS_CART if kind == "cart" else CS_NONCART
+    g.nsamp = int(nsamp)
+    g.sigma = float(sigma)
+    g.kwidth = int(kwidth)
+    g.beta = float(beta)
+    g.wav_levels = int(wav_levels)
+    return g
+
+
+def workspace_size(shape, ncoil, kind="cart", nsamp=0, sigma=1.25, kwidth=4, beta=0.0,
+                   wav_levels=4):
+    """cs_workspace_size for a geometry (no device work)."""
+    lib = load()
+    g = _geom(shape, ncoil, kind, nsamp, sigma, kwidth, beta, wav_levels)
+    nb = ctypes.c_size_t()
+    rc = lib.cs_workspace_size(ctypes.byref(g), ctypes.byref(nb))
+    if rc != 0:
+        raise CSError(f"cs_workspace_size failed ({rc}): {lib.cs_last_error(None).decode()}")
+    return int(nb.value)
+
+
 class Context:
     """One operator geometry bound to the current HIP stream."""
 
     def __init__(self, shape, ncoil, kind="cart", nsamp=0, sigma=1.25, kwidth=4,
-                 beta=0.0, wav_levels=4, device=None):
+                 beta=0.0, wav_levels=4, device=None, workspace=False):
+        """workspace=True: the work buffers come from a torch byte tensor of
+        cs_workspace_size() bytes held by this object (cs_create_ws)."""
         self.lib = load()
         self.shape = tuple(int(s) for s in shape)
         self.ndim = len(self.shape)
@@ -248,8 +284,17 @@ class Context:
         g.beta = float(beta)
         g.wav_levels = int(wav_levels)
         self._ctx = ctypes.c_void_p()
-        rc = self.lib.cs_create(ctypes.byref(g), ctypes.c_void_p(self.stream.cuda_stream),
-                                ctypes.byref(self._ctx))
+        self.workspace = None
+        if workspace:
+            nb = workspace_size(self.shape, ncoil, kind, nsamp, sigma, kwidth, beta, wav_levels)
+            # torch's caching allocator hands out 512-byte aligned blocks
+            self.workspace = torch.empty(nb, dtype=torch.uint8, device=self.device)
+            rc = self.lib.cs_create_ws(ctypes.byref(g), _ptr(self.workspace), nb,
+                                       ctypes.c_void_p(self.stream.cuda_stream),
+                                       ctypes.byref(self._ctx))
+        else:
+            rc = self.lib.cs_create(ctypes.byref(g), ctypes.c_void_p(self.stream.cuda_stream),
+                                    ctypes.byref(self._ctx))
         if rc != 0:
             raise CSError(f"cs_create failed ({rc}): {self.lib.cs_last_error(None).decode()}")
         self._keep = {}
@@ -446,6 +491,36 @@ class Context:
                                          Mr.ctypes.data_as(ctypes.c_void_p), cout, _ptr(out)),
                     "cs_coil_mix")
         return out
+
+    def set_basis(self, U, lam=None):
+        """cs_set_basis: U complex [C, C] (column j = eigenvector j)."""
+        import numpy as np
+        U = np.asarray(U, dtype=np.complex128)
+        if U.shape != (self.C, self.C):
+            raise ValueError("U must be [C, C]")
+        Ur = np.ascontiguousarray(np.stack([U.real, U.imag], -1))
+        lr = None if lam is None else np.ascontiguousarray(np.asarray(lam, dtype=np.float64))
+        if lr is not None and lr.shape != (self.C,):
+            raise ValueError("lam must be [C]")
+        self._check(self.lib.cs_set_basis(
+            self._ctx, Ur.ctypes.data_as(ctypes.c_void_p),
+            None if lr is None else lr.ctypes.data_as(ctypes.c_void_p)), "cs_set_basis")
+
+    def set_sketch(self, V, S, R=None):
+        """cs_set_sketch: R real [S, C - V] used as given; None returns to the draw."""
+        import numpy as np
+        if R is None:
+            self._check(self.lib.cs_set_sketch(self._ctx, int(V), int(S), None), "cs_set_sketch")
+            return
+        R = np.ascontiguousarray(np.asarray(R, dtype=np.float64))
+        if R.shape != (S, self.C - V):
+            raise ValueError("R must be [S, C - V]")
+        self._check(self.lib.cs_set_sketch(self._ctx, int(V), int(S),
+                                           R.ctypes.data_as(ctypes.c_void_p)), "cs_set_sketch")
+
+    def reserve_recon(self, C0=0, init_coils=0):
+        self._check(self.lib.cs_reserve_recon(self._ctx, int(C0), int(init_coils)),
+                    "cs_reserve_recon")
 
     def coil_mix_noalloc(self, inp, M, out):
         """cs_coil_mix_noalloc: M a device complex128 tensor [cout, cin]; out

@@ -3,6 +3,7 @@
 // (Sec. 2.3.2-2.3.3, Eqs. 11-13) and Algorithm 1 with FISTA inner solves
 // (Sec. 2.3.4, Sec. 3.3.1).
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 
@@ -304,8 +305,7 @@ int nc_normal(cs_ctx* c, const float2* maps, int ldc, int c0, int cb, const floa
   float2* G = nullptr;
   CS_TRY(nc_forward(c, x, maps, ldc, c0, cb, &G));
   float2* other = G == c->gridA ? c->gridB : c->gridA;
-  CS_TRY(launch_interp(c, G, cb, W_FULL, c->vbuf, cb, 0, 0));
-  CS_TRY(launch_spread(c, c->vbuf, cb, other));
+  CS_TRY(grid_normal(c, G, cb, other));
   return nc_adjoint_grid(c, other, G, maps, ldc, c0, cb, out);
 }
 
@@ -313,13 +313,12 @@ int nc_apply(cs_ctx* c, const float2* maps, int ldc, int c0, int cb, const float
              float2* y) {
   float2* G = nullptr;
   CS_TRY(nc_forward(c, x, maps, ldc, c0, cb, &G));
-  return launch_interp(c, G, cb, W_SQRT, y, ldc, c0, 1);
+  return grid_interp(c, G, cb, y, ldc, c0);
 }
 
 int nc_adjoint(cs_ctx* c, const float2* maps, int ldc, int c0, int cb, const float2* y,
                float2* out) {
-  CS_TRY(launch_gather_samples(c, y, ldc, c0, cb, c->vbuf));
-  CS_TRY(launch_spread(c, c->vbuf, cb, c->gridA));
+  CS_TRY(grid_spread_data(c, y, ldc, c0, cb, c->gridA));
   return nc_adjoint_grid(c, c->gridA, c->gridB, maps, ldc, c0, cb, out);
 }
 
@@ -369,9 +368,31 @@ int upload_table(cs_ctx* c, float** dst, const std::vector<float>& v) {
   return CS_OK;
 }
 
-int create_impl(const cs_geom* g, void* stream, cs_ctx** out) {
-  if (!g || !out) return fail(nullptr, CS_EINVAL, "null argument");
-  *out = nullptr;
+// FFT plans (twiddle tables) of every transform length the operator uses,
+// made here so that no operator call allocates.  A length with a prime
+// factor other than 2, 3, 5 gets no plan: the context still serves the
+// building blocks, and every FFT on that length fails with CS_EINVAL (before
+// any allocation).
+int create_plans(cs_ctx* c) {
+  std::vector<int> Ls;
+  if (c->g.kind == CS_CART) {
+    Ls = {c->ny, c->nx};
+  } else {
+    Ls = {c->my, c->mx};
+    if (c->ndim == 3) Ls.push_back(c->mz);
+  }
+  for (int L : Ls) {
+    int n = L;
+    for (int f : {2, 3, 5})
+      while (n % f == 0) n /= f;
+    const FFTPlan* p = nullptr;
+    if (n == 1) CS_TRY(get_plan(c, L, &p));
+  }
+  return CS_OK;
+}
+
+// Geometry checks and the derived sizes (no device work).
+int init_geometry(cs_ctx* c, const cs_geom* g) {
   if (g->ndim != 2 && g->ndim != 3) return fail(nullptr, CS_EINVAL, "ndim must be 2 or 3");
   if (g->ncoil < 1 || g->ncoil > 64) return fail(nullptr, CS_EINVAL, "ncoil must be in [1, 64]");
   if (g->kind != CS_CART && g->kind != CS_NONCART) return fail(nullptr, CS_EINVAL, "kind");
@@ -388,10 +409,7 @@ int create_impl(const cs_geom* g, void* stream, cs_ctx** out) {
   for (int a = 0; a < g->ndim; ++a)
     if (g->n[a] % (1 << g->wav_levels) != 0)
       return fail(nullptr, CS_EINVAL, "image size not divisible by 2^wav_levels");
-
-  cs_ctx* c = new cs_ctx();
   c->g = *g;
-  c->stream = (hipStream_t)stream;
   c->ndim = g->ndim;
   c->C = g->ncoil;
   if (g->ndim == 3) {
@@ -414,46 +432,73 @@ int create_impl(const cs_geom* g, void* stream, cs_ctx** out) {
     c->N = c->D;
   }
   c->M = (long long)c->mz * c->my * c->mx;
-  int rc = CS_OK;
-  auto alloc = [&](void** p, size_t bytes) -> int {
-    hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 16));
-    if (e != hipSuccess) return fail(c, CS_EHIP, std::string("hipMalloc: ") + hipGetErrorString(e));
-    return CS_OK;
-  };
+  return CS_OK;
+}
+
+// The context's work buffers: (field, bytes) in a fixed order.  They come
+// from the caller's workspace (each at a 256-byte boundary) or from hipMalloc.
+constexpr size_t kWsAlign = 256;
+size_t ws_round(size_t b) { return (std::max<size_t>(b, 16) + kWsAlign - 1) / kWsAlign * kWsAlign; }
+
+std::vector<std::pair<void**, size_t>> ws_requests(cs_ctx* c) {
   const size_t f2 = sizeof(float2);
-  if ((rc = alloc((void**)&c->gridA, f2 * c->M * kCoilChunk)) ||
-      (rc = alloc((void**)&c->gridB, f2 * c->M * kCoilChunk)) ||
-      (rc = alloc((void**)&c->red, sizeof(double) * 2 * 1024)) ||
-      (rc = alloc((void**)&c->red_out, sizeof(double) * 2 * 1024)) ||
-      (rc = alloc((void**)&c->cov_part, sizeof(double) * 2 * 512 * c->C * c->C)) ||
-      (rc = alloc((void**)&c->cov, sizeof(double) * 2 * c->C * c->C)) ||
-      (rc = alloc((void**)&c->eig_dev, sizeof(double) * (2 * c->C * c->C + c->C))) ||
-      (rc = alloc((void**)&c->vmaps, f2 * c->D * c->C)) ||
-      (rc = alloc((void**)&c->smaps, f2 * c->D * c->C)) ||
-      (rc = alloc((void**)&c->wav1, f2 * c->D)) ||
-      (rc = alloc((void**)&c->wav2, f2 * c->D))) {
-    cs_destroy(c);
-    g_create_error = "allocation failed";
+  const size_t C = (size_t)c->C;
+  std::vector<std::pair<void**, size_t>> r = {
+      {(void**)&c->gridA, f2 * c->M * kCoilChunk},
+      {(void**)&c->gridB, f2 * c->M * kCoilChunk},
+      {(void**)&c->red, sizeof(double) * 2 * 1024},
+      {(void**)&c->red_out, sizeof(double) * 2 * 1024},
+      {(void**)&c->cov_part, sizeof(double) * 2 * 512 * C * C},
+      {(void**)&c->cov, sizeof(double) * 2 * C * C},
+      {(void**)&c->eig_dev, sizeof(double) * (2 * C * C + C)},
+      {(void**)&c->vmaps, f2 * c->D * C},
+      {(void**)&c->smaps, f2 * c->D * C},
+      {(void**)&c->wav1, f2 * c->D},
+      {(void**)&c->wav2, f2 * c->D},
+      {(void**)&c->tvu, f2 * c->D * c->ndim}};
+  c->img.assign(12, nullptr);
+  for (auto& p : c->img) r.push_back({(void**)&p, f2 * c->D});
+  return r;
+}
+
+int create_impl(const cs_geom* g, void* workspace, size_t ws_bytes, void* stream,
+                cs_ctx** out) {
+  if (!g || !out) return fail(nullptr, CS_EINVAL, "null argument");
+  *out = nullptr;
+  cs_ctx* c = new cs_ctx();
+  int rc = init_geometry(c, g);
+  if (rc != CS_OK) {
+    delete c;
     return rc;
   }
-  if (g->kind == CS_NONCART && (rc = alloc((void**)&c->vbuf, f2 * std::max(1LL, c->N) * kCoilChunk))) {
-    cs_destroy(c);
-    g_create_error = "allocation failed";
-    return rc;
-  }
-  for (int i = 0; i < 12; ++i) {
-    float2* p = nullptr;
-    if ((rc = alloc((void**)&p, f2 * c->D))) {
-      cs_destroy(c);
-      g_create_error = "allocation failed";
-      return rc;
+  c->stream = (hipStream_t)stream;
+  if (const char* e = std::getenv("CS_FFT_PIX")) c->fft_pix = std::max(1, std::atoi(e));
+  if (const char* e = std::getenv("CS_FFT_COLS")) c->fft_cols = std::max(1, std::atoi(e));
+  auto reqs = ws_requests(c);
+  if (workspace) {
+    size_t need = 0;
+    for (auto& q : reqs) need += ws_round(q.second);
+    if ((reinterpret_cast<uintptr_t>(workspace) % kWsAlign) != 0 || ws_bytes < need) {
+      delete c;
+      return fail(nullptr, CS_EINVAL,
+                  "workspace must be 256-byte aligned and at least cs_workspace_size() bytes");
     }
-    c->img.push_back(p);
-  }
-  if ((rc = alloc((void**)&c->tvu, f2 * c->D * c->ndim))) {
-    cs_destroy(c);
-    g_create_error = "allocation failed";
-    return rc;
+    c->ws_external = true;
+    char* base = static_cast<char*>(workspace);
+    size_t off = 0;
+    for (auto& q : reqs) {
+      *q.first = base + off;
+      off += ws_round(q.second);
+    }
+  } else {
+    for (auto& q : reqs) {
+      hipError_t e = hipMalloc(q.first, std::max<size_t>(q.second, 16));
+      if (e != hipSuccess) {
+        cs_destroy(c);
+        g_create_error = std::string("hipMalloc: ") + hipGetErrorString(e);
+        return CS_EHIP;
+      }
+    }
   }
   if (hipHostMalloc((void**)&c->host_red, sizeof(double) * 2 * 1024) != hipSuccess) {
     cs_destroy(c);
@@ -486,7 +531,8 @@ int create_impl(const cs_geom* g, void* stream, cs_ctx** out) {
   if ((rc = upload_table(c, &c->da[0], tab[0])) || (rc = upload_table(c, &c->da[1], tab[1])) ||
       (rc = upload_table(c, &c->da[2], tab[2])) || (rc = upload_table(c, &c->dp_z, dpz)) ||
       (rc = upload_table(c, &c->dp_y, dpy)) || (rc = upload_table(c, &c->da_y1d, y1d)) ||
-      (rc = wavelet_init(c)) || (rc = mix_scratch_init(c))) {
+      (rc = wavelet_init(c)) || (rc = mix_scratch_init(c)) || (rc = create_plans(c)) ||
+      (rc = coil_mix_reserve(c))) {
     std::string e = c->err;
     cs_destroy(c);
     g_create_error = e;
@@ -521,6 +567,33 @@ int power_iter(cs_ctx* c, const float2* maps, int ncoil, int n_iter, double* L) 
   return CS_OK;
 }
 
+// a recon buffer of at least `need` complex elements (allocates only when it
+// grows: after cs_reserve_recon with enough room, never)
+int grow_buf(cs_ctx* c, float2** buf, size_t* have, size_t need) {
+  if (need <= *have) return CS_OK;
+  if (*buf) CS_HIP(c, hipFree(*buf));
+  *buf = nullptr;
+  *have = 0;
+  CS_HIP(c, hipMalloc(buf, sizeof(float2) * need));
+  *have = need;
+  return CS_OK;
+}
+
+// virtual maps c'[d][j] = sum_c conj(U[c][j]) c[d][c] from the basis in c->U
+int form_vmaps(cs_ctx* c) {
+  const int C = c->C;
+  std::vector<double> M((size_t)2 * C * C);
+  for (int j = 0; j < C; ++j)
+    for (int cc = 0; cc < C; ++cc) {
+      M[2 * (j * C + cc)] = c->U[2 * (cc * C + j)];
+      M[2 * (j * C + cc) + 1] = -c->U[2 * (cc * C + j) + 1];
+    }
+  CS_TRY(coil_mix(c, c->maps, C, 0, C, M.data(), C, c->vmaps, C, 0, 1.0f));
+  c->have_U = true;
+  ++c->vmaps_gen;
+  return CS_OK;
+}
+
 int sketch_impl(cs_ctx* c, const float2* y, int V, int S, uint64_t seed, int t, int refresh,
                 float2* smaps, std::vector<int8_t>* signs_out) {
   const int C = c->C;
@@ -532,27 +605,33 @@ int sketch_impl(cs_ctx* c, const float2* y, int V, int S, uint64_t seed, int t, 
   if (!c->have_U || refresh) {
     if (!y) return fail(c, CS_EINVAL, "y is required for the first sketch");
     CS_TRY(covariance_eig(c, y));
-    // virtual maps c'[d][j] = sum_c conj(U[c][j]) c[d][c]
-    std::vector<double> M((size_t)2 * C * C);
-    for (int j = 0; j < C; ++j)
-      for (int cc = 0; cc < C; ++cc) {
-        M[2 * (j * C + cc)] = c->U[2 * (cc * C + j)];
-        M[2 * (j * C + cc) + 1] = -c->U[2 * (cc * C + j) + 1];
-      }
-    CS_TRY(coil_mix(c, c->maps, C, 0, C, M.data(), C, c->vmaps, C, 0, 1.0f));
-    c->have_U = true;
+    CS_TRY(form_vmaps(c));
   }
   const int Ch = V + S;
-  if (V > 0) {
+  // the V identity rows (the high-energy virtual coils) are the same at
+  // every outer iteration: the context's own sketched maps keep them from
+  // the first draw on the current virtual maps with this layout
+  const bool own = smaps == c->smaps;
+  if (V > 0 && !(own && c->vrows_gen == c->vmaps_gen && c->vrows_V == V && c->vrows_Ch == Ch)) {
     std::vector<double> I((size_t)2 * V * V, 0.0);
     for (int j = 0; j < V; ++j) I[2 * (j * V + j)] = 1.0;
     CS_TRY(coil_mix(c, c->vmaps, C, 0, V, I.data(), V, smaps, Ch, 0, 1.0f));
+    if (own) {
+      c->vrows_gen = c->vmaps_gen;
+      c->vrows_V = V;
+      c->vrows_Ch = Ch;
+    }
   }
   std::vector<int8_t> sg;
   if (S > 0 && V < Ce) {
     const int cols = Ce - V;
     std::vector<double> R((size_t)2 * S * cols, 0.0);
-    if (c->sketch_dist == CS_SKETCH_GAUSSIAN) {
+    float scale = (float)(1.0 / std::sqrt((double)S));
+    if (c->inj_S == S && c->inj_V == V && c->inj_R.size() == (size_t)S * cols) {
+      // injected block, used as given (its scale included)
+      for (size_t e = 0; e < c->inj_R.size(); ++e) R[2 * e] = c->inj_R[e];
+      scale = 1.0f;
+    } else if (c->sketch_dist == CS_SKETCH_GAUSSIAN) {
       std::vector<double> gv;
       gaussian(seed, t, S, cols, gv);
       for (int a = 0; a < S; ++a)
@@ -562,8 +641,7 @@ int sketch_impl(cs_ctx* c, const float2* y, int V, int S, uint64_t seed, int t, 
       for (int a = 0; a < S; ++a)
         for (int b = 0; b < cols; ++b) R[2 * (a * cols + b)] = (double)sg[(size_t)a * cols + b];
     }
-    CS_TRY(coil_mix(c, c->vmaps, C, V, cols, R.data(), S, smaps, Ch, V,
-                    (float)(1.0 / std::sqrt((double)S))));
+    CS_TRY(coil_mix(c, c->vmaps, C, V, cols, R.data(), S, smaps, Ch, V, scale));
   }
   if (signs_out) *signs_out = sg;
   return CS_OK;
@@ -665,7 +743,23 @@ using namespace cs;
 extern "C" {
 
 int cs_create(const cs_geom* g, void* stream, cs_ctx** out) {
-  return create_impl(g, stream, out);
+  return create_impl(g, nullptr, 0, stream, out);
+}
+
+int cs_workspace_size(const cs_geom* g, size_t* bytes) {
+  if (!g || !bytes) return fail(nullptr, CS_EINVAL, "null argument");
+  cs_ctx tmp;
+  CS_TRY(init_geometry(&tmp, g));
+  size_t need = 0;
+  for (auto& q : ws_requests(&tmp)) need += ws_round(q.second);
+  *bytes = need;
+  return CS_OK;
+}
+
+int cs_create_ws(const cs_geom* g, void* workspace, size_t ws_bytes, void* stream,
+                 cs_ctx** out) {
+  if (!workspace) return fail(nullptr, CS_EINVAL, "workspace is null");
+  return create_impl(g, workspace, ws_bytes, stream, out);
 }
 
 void cs_destroy(cs_ctx* c) {
@@ -674,19 +768,21 @@ void cs_destroy(cs_ctx* c) {
   auto fr = [](void* p) {
     if (p) (void)hipFree(p);
   };
-  fr(c->gridA); fr(c->gridB); fr(c->vbuf); fr(c->red); fr(c->red_out);
-  fr(c->cov_part); fr(c->cov); fr(c->eig_dev); fr(c->vmaps); fr(c->smaps);
-  fr(c->wav1); fr(c->wav2); fr(c->mask); fr(c->rec); fr(c->dcf_orig);
+  if (!c->ws_external) {  // buffers carved from a caller's workspace stay theirs
+    fr(c->gridA); fr(c->gridB); fr(c->red); fr(c->red_out);
+    fr(c->cov_part); fr(c->cov); fr(c->eig_dev); fr(c->vmaps); fr(c->smaps);
+    fr(c->wav1); fr(c->wav2); fr(c->tvu);
+    for (auto* p : c->img) fr(p);
+  }
+  fr(c->mask); fr(c->rec); fr(c->vbuf); fr(c->dcf_orig);
   fr(c->mixB); fr(c->ones);
   for (int k = 0; k < cs_ctx::kStage; ++k) {
     if (c->stage[k]) (void)hipHostFree(c->stage[k]);
     if (c->stage_ev[k]) (void)hipEventDestroy(c->stage_ev[k]);
   }
-  fr(c->items); fr(c->item_off); fr(c->partial);
+  fr(c->gitems); fr(c->item_off); fr(c->partial);
   for (int a = 0; a < 3; ++a) fr(c->da[a]);
   fr(c->dp_z); fr(c->dp_y); fr(c->da_y1d);
-  for (auto* p : c->img) fr(p);
-  fr(c->tvu);
   fr(c->ysk);
   fr(c->cmaps);
   fr(c->ycmp);
@@ -731,11 +827,13 @@ int cs_set_operator(cs_ctx* c, const void* maps, const uint8_t* mask, const floa
     if (!coords && c->N > 0) return fail(c, CS_EINVAL, "non-Cartesian operator needs coordinates");
     if (c->rec) {
       CS_HIP(c, hipFree(c->rec)); c->rec = nullptr;
-      CS_HIP(c, hipFree(c->items)); c->items = nullptr;
+      CS_HIP(c, hipFree(c->vbuf)); c->vbuf = nullptr;
+      CS_HIP(c, hipFree(c->gitems)); c->gitems = nullptr;
       CS_HIP(c, hipFree(c->item_off)); c->item_off = nullptr;
       CS_HIP(c, hipFree(c->partial)); c->partial = nullptr;
       c->n_items = 0;
       c->partial_elems = 0;
+      c->group_off.clear();
     }
     if (c->dcf_orig) {
       CS_HIP(c, hipFree(c->dcf_orig));
@@ -774,6 +872,50 @@ int sketch_build(cs_ctx* c, const void* y, int V, int S, uint64_t seed, int t, i
   if (U_out) std::memcpy(U_out, c->U.data(), sizeof(double) * 2 * c->C * c->C);
   if (signs && !sg.empty()) std::memcpy(signs, sg.data(), sg.size());
   if (eig || U_out || signs) CS_HIP(c, hipStreamSynchronize(c->stream));
+  return CS_OK;
+}
+
+int cs_reserve_recon(cs_ctx* c, int C0, int init_coils) {
+  if (!c) return CS_EINVAL;
+  if (C0 < 0 || C0 > c->C || init_coils < 0 || init_coils > c->C)
+    return fail(c, CS_EINVAL, "cs_reserve_recon: C0 and init_coils must be in [0, C]");
+  const size_t Nd = (size_t)std::max(1LL, c->N);
+  if (C0 > 0) {
+    CS_TRY(grow_buf(c, &c->cmaps, &c->cmaps_elems, (size_t)c->D * C0));
+    CS_TRY(grow_buf(c, &c->ycmp, &c->ycmp_elems, Nd * C0));
+  }
+  if (init_coils > 0) CS_TRY(grow_buf(c, &c->ysk, &c->ysk_elems, Nd * init_coils));
+  return CS_OK;
+}
+
+int cs_set_basis(cs_ctx* c, const double* U, const double* lam) {
+  if (!c) return CS_EINVAL;
+  if (!c->have_op) return fail(c, CS_EINVAL, "cs_set_operator has not been called");
+  if (!U) return fail(c, CS_EINVAL, "U is null");
+  const int C = c->C;
+  for (int i = 0; i < 2 * C * C; ++i)
+    if (!std::isfinite(U[i])) return fail(c, CS_EINVAL, "U has a non-finite entry");
+  c->U.assign(U, U + 2 * C * C);
+  if (lam) c->lam.assign(lam, lam + C);
+  else c->lam.assign(C, 0.0);
+  return form_vmaps(c);
+}
+
+int cs_set_sketch(cs_ctx* c, int V, int S, const double* R) {
+  if (!c) return CS_EINVAL;
+  if (!R) {
+    c->inj_R.clear();
+    c->inj_V = c->inj_S = -1;
+    return CS_OK;
+  }
+  if (V < 0 || S < 1 || V + S > c->C || V >= c->C)
+    return fail(c, CS_EINVAL, "cs_set_sketch: need V >= 0, S >= 1, V + S <= C and V < C");
+  const size_t n = (size_t)S * (c->C - V);
+  for (size_t e = 0; e < n; ++e)
+    if (!std::isfinite(R[e])) return fail(c, CS_EINVAL, "R has a non-finite entry");
+  c->inj_R.assign(R, R + n);
+  c->inj_V = V;
+  c->inj_S = S;
   return CS_OK;
 }
 
@@ -983,17 +1125,8 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
   if (compress) {
     const int C0 = p->C0;
     if (!c->have_U) CS_TRY(sketch_impl(c, y, C0, 0, p->seed, p->t0, 0, c->smaps, nullptr));
-    auto grow = [&](float2** buf, size_t* have, size_t need) -> int {
-      if (need <= *have) return CS_OK;
-      if (*buf) CS_HIP(c, hipFree(*buf));
-      *buf = nullptr;
-      *have = 0;
-      CS_HIP(c, hipMalloc(buf, sizeof(float2) * need));
-      *have = need;
-      return CS_OK;
-    };
-    CS_TRY(grow(&c->cmaps, &c->cmaps_elems, (size_t)c->D * C0));
-    CS_TRY(grow(&c->ycmp, &c->ycmp_elems, (size_t)std::max(1LL, c->N) * C0));
+    CS_TRY(grow_buf(c, &c->cmaps, &c->cmaps_elems, (size_t)c->D * C0));
+    CS_TRY(grow_buf(c, &c->ycmp, &c->ycmp_elems, (size_t)std::max(1LL, c->N) * C0));
     // first C0 rows of U^H: M[j][cc] = conj(U[cc][j])
     std::vector<double> M((size_t)2 * C0 * C);
     for (int j = 0; j < C0; ++j)
@@ -1069,14 +1202,7 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
           M[2 * ((V + i) * C + cc) + 1] -= w * c->U[2 * (cc * C + V + bb) + 1];
         }
     }
-    const size_t need = (size_t)std::max(1LL, c->N) * Ch;
-    if (need > c->ysk_elems) {
-      if (c->ysk) CS_HIP(c, hipFree(c->ysk));
-      c->ysk = nullptr;
-      c->ysk_elems = 0;
-      CS_HIP(c, hipMalloc(&c->ysk, sizeof(float2) * need));
-      c->ysk_elems = need;
-    }
+    CS_TRY(grow_buf(c, &c->ysk, &c->ysk_elems, (size_t)std::max(1LL, c->N) * Ch));
     CS_TRY(coil_mix_rows(c, c->N, y, C, 0, C, M.data(), Ch, c->ysk, Ch, 0, 1.0f));
     CS_TRY(sketch_impl(c, y, p->V, p->S, p->seed, 0, 0, c->smaps, nullptr));
     float2* bs = c->img[10];

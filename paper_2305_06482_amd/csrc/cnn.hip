@@ -329,6 +329,10 @@ struct cs_cnn {
   double* dpart = nullptr;  // loss partials
   double* dsum = nullptr;
   double* host = nullptr;   // pinned readback
+  // orders the network's stream and a reconstruction context's stream around
+  // a warm start (they may differ): net_done is recorded on the network's
+  // stream before the forward pass, ctx_done on the context's stream after
+  hipEvent_t net_done = nullptr, ctx_done = nullptr;
   std::string err;
 };
 
@@ -465,12 +469,25 @@ int cnn_warm_start(cs_cnn* n, cs_ctx* c, const float2* x, const float2* d, float
   if (c->ndim != 3 && c->ndim != 2) return fail(c, CS_EINVAL, "CNN volume");
   const int nz = c->ndim == 3 ? c->nz : 1;
   if (ensure(n, c->D) != CS_OK) return fail(c, CS_EHIP, "CNN buffers: " + n->err);
+  // the forward pass below runs on the context stream but reads the
+  // parameters and fragments that training steps write on the network's
+  // stream, and writes the activations those steps also use: wait for the
+  // network's earlier work first, and make its later work wait for this
+  const bool other = n->stream != c->stream;
+  if (other) {
+    CS_HIP(c, hipEventRecord(n->net_done, n->stream));
+    CS_HIP(c, hipStreamWaitEvent(c->stream, n->net_done, 0));
+  }
   CS_TRY(cnn_pack_input(c, x, d, sx, sd, n->act[0]));
   if (forward(n, nz, c->ny, c->nx, c->stream) != CS_OK)
     return fail(c, CS_EHIP, "CNN forward: " + n->err);
   hipLaunchKernelGGL(k_apply_delta, dim3(blocks(c->D, 256)), dim3(256), 0, c->stream, x,
                      n->act[kL], c->D, so, z0);
   CS_HIP(c, hipGetLastError());
+  if (other) {
+    CS_HIP(c, hipEventRecord(n->ctx_done, c->stream));
+    CS_HIP(c, hipStreamWaitEvent(n->stream, n->ctx_done, 0));
+  }
   return CS_OK;
 }
 
@@ -513,7 +530,9 @@ int cs_cnn_create(void* stream, uint64_t seed, cs_cnn** out) {
             hipMalloc(&n->m2, sizeof(float) * off) == hipSuccess &&
             hipMalloc(&n->dpart, sizeof(double) * kRB) == hipSuccess &&
             hipMalloc(&n->dsum, sizeof(double)) == hipSuccess &&
-            hipHostMalloc((void**)&n->host, sizeof(double) * 2, 0) == hipSuccess;
+            hipHostMalloc((void**)&n->host, sizeof(double) * 2, 0) == hipSuccess &&
+            hipEventCreateWithFlags(&n->net_done, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&n->ctx_done, hipEventDisableTiming) == hipSuccess;
   for (int l = 0; l < kL && ok; ++l)
     ok = hipMalloc(&n->fwd[l], sizeof(v4s) * 64 * n->fwd_nk[l] * n->fwd_nt[l]) == hipSuccess &&
          hipMalloc(&n->bwd[l], sizeof(v4s) * 64 * n->bwd_nk[l] * n->bwd_nt[l]) == hipSuccess;
@@ -552,6 +571,8 @@ void cs_cnn_destroy(cs_cnn* n) {
     fr(n->gact[l]);
   }
   if (n->host) (void)hipHostFree(n->host);
+  if (n->net_done) (void)hipEventDestroy(n->net_done);
+  if (n->ctx_done) (void)hipEventDestroy(n->ctx_done);
   delete n;
 }
 

@@ -58,14 +58,27 @@ struct PassArgs {
   const float* dp;       // [P] per-pixel scale of the other axes
 };
 
-// Sample record of the sorted non-Cartesian trajectory (80 bytes).
+// Sample record of the sorted non-Cartesian trajectory (64 bytes): first tap
+// relative to the tile's origin (x | y << 8 | z << 16), density weight w and
+// sqrt(w), index in the caller's order, and the four kernel weights per axis.
 struct SampleRec {
-  int bx, by, bz;        // first tap index per axis, wrapped into [0, m)
-  int orig;              // index of the sample in the caller's order
-  float w, sw;           // density compensation w and sqrt(w)
-  float pad0, pad1;
+  int key;
+  float w, sw;
+  int orig;
   float wx[4], wy[4], wz[4];
 };
+
+// A work item of the gridding kernels: samples kbeg .. kend (sorted order) of
+// one tile; slot = its partial tile (items of tile t hold slots item_off[t] ..
+// item_off[t + 1]); voff = the offset of its values in its item group.
+struct GridItem {
+  int tile, kbeg, kend, slot, voff, pad0, pad1, pad2;
+};
+
+
+// samples per item group of the normal operator by default (its values stay
+// on chip between the interpolation and the spreading)
+constexpr long long kGroupSamples = 1LL << 40;
 
 struct FFTPlan {
   int L = 0;
@@ -90,6 +103,9 @@ struct cs_ctx {
   float beta = 0.f;
 
   std::map<int, cs::FFTPlan> plans;
+  // FFT pass panels: pixels per panel of an image pass (all coils of each)
+  // and columns per panel of a grid pass (CS_FFT_PIX / CS_FFT_COLS)
+  int fft_pix = 1, fft_cols = 16;
 
   // operator
   const float2* maps = nullptr;   // borrowed [D][C]
@@ -103,12 +119,13 @@ struct cs_ctx {
   float* ones = nullptr;          // [max(n)] ones
 
   // non-Cartesian
-  cs::SampleRec* rec = nullptr;   // [N] sorted
+  cs::SampleRec* rec = nullptr;   // [N] sorted sample records
   float* dcf_orig = nullptr;      // [N] caller order (nullptr: w = 1)
   int tile[3] = {1, 1, 1};        // spread tile size (tz, ty, tx)
   int ntile[3] = {1, 1, 1};
   long long ntiles = 0;
-  int4* items = nullptr;          // spread work items (tile, kbeg, kend, slot), heavy first
+  cs::GridItem* gitems = nullptr; // work items, grouped (group g: group_off[g] .. [g + 1])
+  std::vector<int> group_off;
   long long n_items = 0;
   int* item_off = nullptr;        // [ntiles + 1]: slots of tile t are item_off[t]..[t+1]
   float2* partial = nullptr;      // halo'd partial tile of every slot
@@ -118,9 +135,11 @@ struct cs_ctx {
   int sketch_dist = 0;            // CS_SKETCH_RADEMACHER or CS_SKETCH_GAUSSIAN
 
   // work buffers
+  bool ws_external = false;       // carved from the caller's workspace (not freed here)
   float2* gridA = nullptr;        // M * kCoilChunk
   float2* gridB = nullptr;
-  float2* vbuf = nullptr;         // N * kCoilChunk (non-Cartesian)
+  float2* vbuf = nullptr;         // sample values of the largest item group (kCoilChunk coils)
+  long long vbuf_pad = 0;         // extra coils allocated past its last row
   std::vector<float2*> img;       // D-sized scratch images
   double* red = nullptr;          // reduction partials
   double* red_out = nullptr;      // final reduction values (device)
@@ -140,6 +159,14 @@ struct cs_ctx {
   std::vector<double> U;          // C*C complex (re, im) row-major
   std::vector<double> lam;
   float2* vmaps = nullptr;        // [D][C] virtual maps U^H c
+  unsigned long long vmaps_gen = 1;   // bumped whenever vmaps is recomputed
+  // injected random block of the sketch (cs_set_sketch): [S][C - V] as applied
+  std::vector<double> inj_R;
+  int inj_V = -1, inj_S = -1;
+  // layout of the V identity rows last copied into smaps (from vmaps of
+  // generation vrows_gen, V rows of a Ch-coil stack)
+  unsigned long long vrows_gen = 0;
+  int vrows_V = -1, vrows_Ch = -1;
   double* cov_part = nullptr;     // covariance partials
   double* cov = nullptr;          // [C][C] complex double
   double* eig_dev = nullptr;      // U and lambda from the eigensolver
@@ -210,13 +237,14 @@ int get_plan(cs_ctx* c, int L, const FFTPlan** out);
 int launch_pass(cs_ctx* c, PassArgs& a, long long n_outer);
 void fill_plan(PassArgs& a, const FFTPlan* p);
 
-// grid.hip
+// grid.hip (cb <= kCoilChunk coils per call)
 int setup_noncart(cs_ctx* c, const float* coords, const float* dcf);
-int launch_interp(cs_ctx* c, const float2* grid, int cb, int weight_mode,
-                  float2* out, int out_ldc, int out_c0, int caller_order);
-int launch_spread(cs_ctx* c, const float2* vals, int cb, float2* grid);
-int launch_gather_samples(cs_ctx* c, const float2* y, int ldc, int c0, int cb,
-                          float2* vals);
+// out_grid = spread(w * interp(grid)): the gridding stage of the normal operator
+int grid_normal(cs_ctx* c, const float2* grid, int cb, float2* out_grid);
+// y[caller order][c0 + j] = sqrt(w) interp(grid)_j
+int grid_interp(cs_ctx* c, const float2* grid, int cb, float2* y, int ldc, int c0);
+// out_grid = spread(sqrt(w) y[.][c0 + j])
+int grid_spread_data(cs_ctx* c, const float2* y, int ldc, int c0, int cb, float2* out_grid);
 enum { W_NONE = 0, W_SQRT = 1, W_FULL = 2 };
 double kb_i0(double x);
 double kb_ft(double nu, double W, double beta);
@@ -256,6 +284,7 @@ int coil_mix_rows(cs_ctx* c, long long rows, const float2* in, int in_ldc, int i
 // fragments go to a static per-device scratch whose address mix_scratch_init
 // looks up once per device
 int mix_scratch_init(cs_ctx* c);
+int coil_mix_reserve(cs_ctx* c);
 int coil_mix_noalloc(cs_ctx* c, const float2* in, int cin, const void* M, int cout,
                      float2* out);
 

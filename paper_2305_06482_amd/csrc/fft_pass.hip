@@ -252,9 +252,16 @@ __device__ __forceinline__ void dftR(float2* v, int dir) {
 
 // DIR (-1 forward, +1 inverse) is a template parameter so that the
 // multiplications by +-i and the twiddle conjugation fold at compile time
+// a column group of TC columns uses TR = 256 / TC rows of threads (NT = TR TC
+// threads, 252 for TC = 12)
+template <int TC>
+constexpr int pass_rows() {
+  return 256 / TC;
+}
+
 template <int L, int TC, int R, int NS, int DIR>
 __device__ __forceinline__ void fft_stage(float2* buf, const float2* tw, int tr, int tc) {
-  constexpr int TR = 256 / TC;
+  constexpr int TR = pass_rows<TC>();
   constexpr int NBF = L / R;
   constexpr int NB = (NBF + TR - 1) / TR;
   constexpr int TSTEP = L / (NS * R);
@@ -312,7 +319,8 @@ __device__ __forceinline__ void fft_panel(float2* buf, const float2* tw, int tr,
 
 template <int L, int TC>
 __global__ __launch_bounds__(256) void k_pass_t(PassArgs a) {
-  constexpr int TR = 256 / TC;
+  constexpr int TR = pass_rows<TC>();
+  constexpr int NT = TR * TC;
   extern __shared__ float2 smem[];
   float2* buf = smem;             // [L][TC]
   float2* tw = smem + L * TC;     // [L]
@@ -327,7 +335,7 @@ __global__ __launch_bounds__(256) void k_pass_t(PassArgs a) {
   const long long p = colok ? ci / a.cb : 0;
   const int c = colok ? (int)(ci - p * a.cb) : 0;
 
-  for (int i = tid; i < L; i += 256) tw[i] = a.tw[i];
+  for (int i = tid; i < L; i += NT) tw[i] = a.tw[i];
   if (a.n_in < L)
     for (int r = tr; r < L; r += TR) buf[r * TC + tc] = make_float2(0.f, 0.f);
   __syncthreads();
@@ -392,11 +400,27 @@ __global__ __launch_bounds__(256) void k_pass_t(PassArgs a) {
 
 using PassKernel = void (*)(PassArgs);
 
+// column-group widths with a kernel: 12 and 24 / 48 fit 12-coil panels
+// (one, two or four pixels), 16 / 32 / 64 the powers of two
+constexpr int kPassTC[6] = {12, 16, 24, 32, 48, 64};
+
+int pass_tc_for(int w) {
+  for (int tc : kPassTC)
+    if (w <= tc) return tc;
+  return 0;
+}
+
 template <int L>
 PassKernel pick_tc(int TC) {
-  if (TC <= 16) return k_pass_t<L, 16>;
-  if (TC <= 32) return k_pass_t<L, 32>;
-  return k_pass_t<L, 64>;
+  switch (TC) {
+    case 12: return k_pass_t<L, 12>;
+    case 16: return k_pass_t<L, 16>;
+    case 24: return k_pass_t<L, 24>;
+    case 32: return k_pass_t<L, 32>;
+    case 48: return k_pass_t<L, 48>;
+    case 64: return k_pass_t<L, 64>;
+    default: return nullptr;
+  }
 }
 
 PassKernel specialised(int L, int TC) {
@@ -473,18 +497,22 @@ int launch_pass(cs_ctx* c, PassArgs& a, long long n_outer) {
   if (image_cols && (a.inner % a.cb) != 0)
     return fail(c, CS_EINVAL, "image pass columns not a multiple of the coil count");
   if (specialised(L, 16) != nullptr && a.cb <= 64) {
-    // widest column group with at most 16 elements per thread (registers)
-    // whose single LDS buffer fits an 80 KiB budget
-    int tcmax = 64;
-    while (tcmax > 16 && ((long long)L * tcmax > 4096 ||
-                          sizeof(float2) * ((size_t)L * tcmax + L) > 80 * 1024))
-      tcmax /= 2;
-    long long w = tcmax;
-    if (image_cols) w = std::max<long long>(a.cb, (tcmax / a.cb) * a.cb);
+    // panel width: image passes take whole pixels (c->fft_pix of them, all
+    // coils of each), grid passes c->fft_cols columns; the column group is
+    // the narrowest kernel width that holds the panel, kept to at most 40
+    // elements per thread (registers) and a 96 KiB LDS buffer
+    long long w = image_cols ? (long long)a.cb * std::max(1, c->fft_pix) : c->fft_cols;
     if (w > a.inner) w = a.inner;
-    int TC = 16;
-    while (TC < w) TC *= 2;
-    if (TC <= 64) {
+    auto fits = [&](int tc) {
+      return tc > 0 && (long long)L * tc <= 40LL * 256 &&
+             sizeof(float2) * ((size_t)L * tc + L) <= 96 * 1024;
+    };
+    int TC = pass_tc_for((int)w);
+    while (!fits(TC) && w > (image_cols ? a.cb : 1)) {
+      w = image_cols ? std::max<long long>(a.cb, w - a.cb) : std::max<long long>(1, w / 2);
+      TC = pass_tc_for((int)w);
+    }
+    if (fits(TC)) {
       a.Wt = (int)w;
       const long long nblk = (a.inner + a.Wt - 1) / a.Wt;
       a.nblk = nblk;
@@ -495,7 +523,8 @@ int launch_pass(cs_ctx* c, PassArgs& a, long long n_outer) {
       if (lds > 64 * 1024)
         CS_HIP(c, hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)lds));
-      CS_KLAUNCH(c, K_PASS, k, dim3((unsigned)(nblk * n_outer)), dim3(256), lds, c->stream, a);
+      const int nt = (256 / TC) * TC;
+      CS_KLAUNCH(c, K_PASS, k, dim3((unsigned)(nblk * n_outer)), dim3(nt), lds, c->stream, a);
       CS_HIP(c, hipGetLastError());
       return CS_OK;
     }

@@ -3,24 +3,30 @@
 // A = W^1/2 F C (Sec. 2.1.1).
 //
 // Set-up (once per operator, host): each sample's grid coordinate
-// u_a = k_a m_a / n_a gives its first tap floor(u_a) - 1 and the four
-// per-axis kernel weights phi(u_a - g) (FP64, stored as FP32).  Samples are
-// sorted by the 8x8x8 (3D) or 16x16 (2D) grid tile that holds their first
-// tap, then by that tap, and each tile's samples are cut into work items of
-// at most 2048 samples.
+// u_a = k_a m_a / n_a gives its first tap floor(u_a) - 1 (wrapped into the
+// grid).  Samples are sorted by the 8x8x8 (3D) or 16x16 (2D) grid tile that
+// holds their first tap, then by that tap, and each tile's samples are cut
+// into work items of at most 2048 samples.  A sample's 64-byte record holds
+// its first tap relative to the tile's origin (packed), w, sqrt(w), its index
+// in the caller's order and the four kernel weights phi(u_a - g) per axis,
+// evaluated in FP64 and stored as FP32.
 //
-// interp: one thread per sorted sample gathers the 4^d taps of every coil of
-//         a coil chunk (coil-fastest grid, so each tap is one contiguous
-//         vector of coils).
+// interp: one work-group per work item and coil group copies the item's
+//         halo'd grid tile (the tile grown by the kernel's 3-voxel reach,
+//         wrapped modulo the grid) into LDS and sums each sample's 4^d taps
+//         from there (one thread per sample).
 // spread: one work-group per work item and coil group accumulates, in LDS,
-//         its samples into the tile grown by the 3-voxel reach of the kernel
-//         (each sample is handled once), one sample at a time with one lane
-//         per tap.  Within a LDS instruction all lanes address distinct
-//         voxels and a wave executes its LDS instructions in order, so every
-//         voxel's summation order is fixed.  The grown tile is written to the
-//         item's slot, and a merge kernel sums, for every grid voxel, the
-//         slots that cover it in a fixed order: deterministic, and no global
-//         atomics.
+//         its samples into the halo'd tile (each sample is handled once),
+//         one sample at a time with one lane per tap.  Within a LDS
+//         instruction all lanes address distinct voxels and a wave executes
+//         its LDS instructions in order, so every voxel's summation order is
+//         fixed.  The halo'd tile is written to the item's slot, and a merge
+//         kernel sums, for every grid voxel, the slots that cover it in a
+//         fixed order: deterministic, and no global atomics.
+// The normal operator W^1/2 W^1/2 between the transforms (Eq. 5) runs
+// interp (x w) and spread over groups of work items whose sample values fit
+// a fixed buffer, so that the values one group's interpolation writes are
+// read back by its spreading from the on-chip caches.
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -65,86 +71,16 @@ double kb_kernel(double t, double W, double beta) {
   return z >= 0 ? kb_i0(beta * std::sqrt(z)) : 0.0;
 }
 
-template <int NDIM, int CBT>
-__global__ __launch_bounds__(256) void k_interp(const float2* __restrict__ G, int mx,
-                                                int my, int mz, int cb,
-                                                const SampleRec* __restrict__ rec,
-                                                long long N, int wmode,
-                                                float2* __restrict__ out, int ldc, int c0,
-                                                int caller_order) {
-  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
-  const SampleRec r = rec[j];
-  float2 acc[CBT];
-#pragma unroll
-  for (int c = 0; c < CBT; ++c) acc[c] = make_float2(0.f, 0.f);
-  int xs[4];
-#pragma unroll
-  for (int d = 0; d < 4; ++d) {
-    int v = r.bx + d;
-    xs[d] = v >= mx ? v - mx : v;
-  }
-  const int nzt = NDIM == 3 ? 4 : 1;
-  // keep the z / y tap loops rolled: unrolling them lets the compiler hoist
-  // all 64 taps' loads and spill
-#pragma unroll 1
-  for (int dz = 0; dz < nzt; ++dz) {
-    int z = r.bz + dz;
-    if (z >= mz) z -= mz;
-    const float wz = NDIM == 3 ? r.wz[dz] : 1.f;
-#pragma unroll 1
-    for (int dy = 0; dy < 4; ++dy) {
-      int y = r.by + dy;
-      if (y >= my) y -= my;
-      const float wyz = wz * r.wy[dy];
-      const long long row = ((long long)z * my + y) * mx;
-#pragma unroll
-      for (int dx = 0; dx < 4; ++dx) {
-        const float w = wyz * r.wx[dx];
-        const float2* p = G + (row + xs[dx]) * cb;
-        if constexpr (CBT % 2 == 0) {
-          // cb == CBT (even): two coils per 16-byte load
-          const float4* p4 = reinterpret_cast<const float4*>(p);
-#pragma unroll
-          for (int c = 0; c < CBT / 2; ++c) {
-            const float4 g = p4[c];
-            acc[2 * c].x += w * g.x;
-            acc[2 * c].y += w * g.y;
-            acc[2 * c + 1].x += w * g.z;
-            acc[2 * c + 1].y += w * g.w;
-          }
-        } else {
-#pragma unroll
-          for (int c = 0; c < CBT; ++c) {
-            if (c < cb) {
-              const float2 g = p[c];
-              acc[c].x += w * g.x;
-              acc[c].y += w * g.y;
-            }
-          }
-        }
-      }
-    }
-  }
-  const float s = wmode == W_FULL ? r.w : (wmode == W_SQRT ? r.sw : 1.f);
-  const long long o = caller_order ? (long long)r.orig : j;
-  float2* dst = out + o * ldc + c0;
-#pragma unroll
-  for (int c = 0; c < CBT; ++c)
-    if (c < cb) dst[c] = make_float2(acc[c].x * s, acc[c].y * s);
-}
-
-
 __device__ __forceinline__ float sel4(const float* w, int i) {
   return i == 0 ? w[0] : (i == 1 ? w[1] : (i == 2 ? w[2] : w[3]));
 }
 
 // Halo'd spread tile: every sample belongs to the one tile that holds its
 // first tap, and its 4^d footprint stays inside the tile grown by 3 voxels
-// along each axis.  The LDS accumulator is planar per (coil, re/im) with
-// voxel offset lz * PZ + ly * PY + lx: dense in 3D (the 64 taps of a sample
-// meet at most two per bank, and only when a run is flushed) and with row
-// pitch 20 in 2D (16 taps in distinct banks).
+// along each axis.  The LDS tiles are planar per (coil, re/im) with voxel
+// offset lz * PZ + ly * PY + lx: dense in 3D (the 64 taps of a sample meet
+// at most two per bank, and only when a run is flushed) and with row pitch
+// 20 in 2D (16 taps in distinct banks).
 template <int NDIM>
 struct Halo {
   static constexpr int TX = NDIM == 3 ? 8 : 16;
@@ -159,84 +95,111 @@ struct Halo {
   static constexpr int LPC = 64 / NTAPS;  // coil slots per wave
 };
 
-// Tiled interpolation: one work-group per spread work item and coil group.
-// The group first copies the item's halo'd tile of the grid (the tile grown
-// by the 3-voxel reach of the kernel, wrapped modulo the grid) into LDS,
-// planar per (coil, re/im) as in the spreading accumulator, and then one
-// thread per sample sums its 4^d taps from LDS in the same order as
-// k_interp (z, y, x taps, weight wz wy wx), so both give the same values.
-// Every tap of a sample lies in the halo'd tile of the tile that holds its
-// first tap, so no other memory is read.
-template <int NDIM, int CG, int NT>
-__global__ __launch_bounds__(NT) void k_interp_tile(
+// Interpolation: one work-group per work item and coil group.  With TILE the
+// group first copies the item's halo'd tile of the grid into LDS, planar per
+// (coil, re/im) as in the spreading accumulator; without it the taps are
+// read from the grid in global memory.  One thread per sample then sums its
+// 4^d taps in the order z, y, x with weight (wz wy) wx, so both variants give
+// the same values.  The sum is scaled by w (W_FULL), sqrt(w) (W_SQRT) or 1,
+// and written to row `voff + k - kbeg` of `out` (values of the item group)
+// or, with caller_order, to row orig[k] (the caller's sample order).
+template <int NDIM, int CG, int NT, bool TILE>
+__global__ __launch_bounds__(NT) void k_interp_items(
     const float2* __restrict__ G, int mx, int my, int mz, int cb,
-    const SampleRec* __restrict__ rec, const int4* __restrict__ items, int ntx, int nty,
-    int wmode, float2* __restrict__ out, int ldc, int c0, int caller_order) {
+    const SampleRec* __restrict__ rec, const GridItem* __restrict__ items, int item0,
+    int ntx, int nty, int wmode, float2* __restrict__ out, int ldc, int c0,
+    int caller_order) {
   using H = Halo<NDIM>;
   extern __shared__ float lds[];  // [CG][2][PLANE]
-  const int4 it = items[blockIdx.x];
-  const int tile = it.x, kbeg = it.y, kend = it.z;
+  const GridItem it = items[item0 + blockIdx.x];
+  const int tile = it.tile, kbeg = it.kbeg, kend = it.kend;
   const int cg0 = blockIdx.y * CG, cga = min(CG, cb - cg0);
   const int ix = tile % ntx, iy = (tile / ntx) % nty, iz = tile / (ntx * nty);
   const int x0 = ix * H::TX, y0 = iy * H::TY, z0 = iz * H::TZ;
   const int tid = threadIdx.x;
-  // one thread per voxel of the halo'd tile copies the group's coils, so the
-  // index arithmetic is paid once per voxel
-  for (int e = tid; e < H::EXT; e += NT) {
-    const int lx = e % H::EX, ly = (e / H::EX) % H::EY, lz = e / (H::EX * H::EY);
-    // wrap into the grid by subtraction (a runtime modulo costs dozens of
-    // instructions): the coordinate is below m + EX - 1 and the grid is at
-    // least 4 long per axis, so (EX + 3) / 4 subtractions suffice
-    int gx = x0 + lx, gy = y0 + ly, gz = NDIM == 3 ? z0 + lz : 0;
+  if constexpr (TILE) {
+    // one thread per voxel of the halo'd tile copies the group's coils, so
+    // the index arithmetic is paid once per voxel
+    for (int e = tid; e < H::EXT; e += NT) {
+      const int lx = e % H::EX, ly = (e / H::EX) % H::EY, lz = e / (H::EX * H::EY);
+      // wrap into the grid by subtraction (a runtime modulo costs dozens of
+      // instructions): the coordinate is below m + EX - 1 and the grid is at
+      // least 4 long per axis, so (EX + 3) / 4 subtractions suffice
+      int gx = x0 + lx, gy = y0 + ly, gz = NDIM == 3 ? z0 + lz : 0;
 #pragma unroll
-    for (int w = 0; w < (H::EX + 3) / 4; ++w) {
-      gx -= gx >= mx ? mx : 0;
-      gy -= gy >= my ? my : 0;
-      if (NDIM == 3) gz -= gz >= mz ? mz : 0;
-    }
-    const float2* src = G + (((long long)gz * my + gy) * mx + gx) * cb + cg0;
-    const int a = lz * H::PZ + ly * H::PY + lx;
+      for (int w = 0; w < (H::EX + 3) / 4; ++w) {
+        gx -= gx >= mx ? mx : 0;
+        gy -= gy >= my ? my : 0;
+        if (NDIM == 3) gz -= gz >= mz ? mz : 0;
+      }
+      const float2* src = G + (((long long)gz * my + gy) * mx + gx) * cb + cg0;
+      const int a = lz * H::PZ + ly * H::PY + lx;
 #pragma unroll
-    for (int q = 0; q < CG; ++q) {
-      float2 v = make_float2(0.f, 0.f);
-      if (q < cga) v = src[q];
-      lds[(size_t)q * 2 * H::PLANE + a] = v.x;
-      lds[(size_t)q * 2 * H::PLANE + H::PLANE + a] = v.y;
+      for (int q = 0; q < CG; ++q) {
+        float2 v = make_float2(0.f, 0.f);
+        if (q < cga) v = src[q];
+        lds[(size_t)q * 2 * H::PLANE + a] = v.x;
+        lds[(size_t)q * 2 * H::PLANE + H::PLANE + a] = v.y;
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();
   for (int k = kbeg + tid; k < kend; k += NT) {
     const SampleRec r = rec[k];
-    const int b0 = (NDIM == 3 ? (r.bz - z0) * H::PZ : 0) + (r.by - y0) * H::PY + (r.bx - x0);
+    const int lx = r.key & 0xff, ly = (r.key >> 8) & 0xff, lz = r.key >> 16;
     float2 acc[CG];
 #pragma unroll
     for (int q = 0; q < CG; ++q) acc[q] = make_float2(0.f, 0.f);
     const int nzt = NDIM == 3 ? 4 : 1;
     // one row of four x taps per step: unrolling further lets the compiler
-    // hoist the LDS reads of many rows and run out of registers.  The row
-    // weights are picked by selects: indexing the record's arrays with a
-    // loop counter would put the record in scratch memory.
+    // hoist the reads of many rows and run out of registers.  The row
+    // weights are picked by selects: indexing the weight arrays with a loop
+    // counter would put them in scratch memory.
 #pragma unroll 1
     for (int dz = 0; dz < nzt; ++dz) {
-      const float wz = NDIM == 3 ? sel4(r.wz, dz) : 1.f;
+      const float wzv = NDIM == 3 ? sel4(r.wz, dz) : 1.f;
 #pragma unroll 1
       for (int dy = 0; dy < 4; ++dy) {
-        const float wyz = wz * sel4(r.wy, dy);
-        const int row = b0 + dz * H::PZ + dy * H::PY;
+        const float wyz = wzv * sel4(r.wy, dy);
+        if constexpr (TILE) {
+          const int row = (lz + dz) * H::PZ + (ly + dy) * H::PY + lx;
 #pragma unroll
-        for (int dx = 0; dx < 4; ++dx) {
-          const float w = wyz * r.wx[dx];
+          for (int dx = 0; dx < 4; ++dx) {
+            const float w = wyz * r.wx[dx];
 #pragma unroll
-          for (int q = 0; q < CG; ++q) {
-            const float* pl = lds + (size_t)q * 2 * H::PLANE + row + dx;
-            acc[q].x += w * pl[0];
-            acc[q].y += w * pl[H::PLANE];
+            for (int q = 0; q < CG; ++q) {
+              const float* pl = lds + (size_t)q * 2 * H::PLANE + row + dx;
+              acc[q].x += w * pl[0];
+              acc[q].y += w * pl[H::PLANE];
+            }
+          }
+        } else {
+          // the first tap x0 + lx lies in [0, m) and m >= 4: one subtraction
+          // wraps a tap
+          int z = z0 + lz + dz, y = y0 + ly + dy;
+          if (NDIM == 3) z -= z >= mz ? mz : 0;
+          y -= y >= my ? my : 0;
+          const long long rowg = ((long long)(NDIM == 3 ? z : 0) * my + y) * mx;
+#pragma unroll
+          for (int dx = 0; dx < 4; ++dx) {
+            const float w = wyz * r.wx[dx];
+            int x = x0 + lx + dx;
+            x -= x >= mx ? mx : 0;
+            const float2* p = G + (rowg + x) * cb + cg0;
+#pragma unroll
+            for (int q = 0; q < CG; ++q) {
+              if (q < cga) {
+                const float2 g = p[q];
+                acc[q].x += w * g.x;
+                acc[q].y += w * g.y;
+              }
+            }
           }
         }
       }
     }
     const float s = wmode == W_FULL ? r.w : (wmode == W_SQRT ? r.sw : 1.f);
-    const long long o = caller_order ? (long long)r.orig : k;
+    const long long o = caller_order ? (long long)r.orig : (long long)(it.voff + k - kbeg);
     float2* dst = out + o * ldc + c0 + cg0;
 #pragma unroll
     for (int q = 0; q < CG; ++q)
@@ -251,20 +214,20 @@ size_t interp_tile_lds_bytes() {
 
 // 512 threads per group in 3D, where the LDS tile allows only one or two
 // groups per compute unit
-template <int NDIM, int CG>
-int interp_tile_launch(cs_ctx* c, const float2* grid, int cb, int wmode, float2* out,
-                       int ldc, int c0, int caller_order) {
-  const size_t lds = interp_tile_lds_bytes<NDIM, CG>();
+template <int NDIM, int CG, bool TILE>
+int interp_launch(cs_ctx* c, const float2* grid, int cb, int item0, int nitems, int wmode,
+                  float2* out, int ldc, int c0, int caller_order) {
+  const size_t lds = TILE ? interp_tile_lds_bytes<NDIM, CG>() : 0;
   if (lds > 160 * 1024) return fail(c, CS_EINVAL, "interpolation tile does not fit in LDS");
   const int ng = (cb + CG - 1) / CG;
-  if (c->n_items == 0) return CS_OK;
+  if (nitems <= 0) return CS_OK;
   constexpr int NT = NDIM == 3 ? 512 : 256;
-  auto kern = k_interp_tile<NDIM, CG, NT>;
+  auto kern = k_interp_items<NDIM, CG, NT, TILE>;
   if (lds > 64 * 1024)
     CS_HIP(c, hipFuncSetAttribute((const void*)kern,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  CS_KLAUNCH(c, K_INTERP, kern, dim3((unsigned)c->n_items, (unsigned)ng), dim3(NT), lds,
-             c->stream, grid, c->mx, c->my, c->mz, cb, c->rec, c->items, c->ntile[2],
+  CS_KLAUNCH(c, K_INTERP, kern, dim3((unsigned)nitems, (unsigned)ng), dim3(NT), lds, c->stream,
+             grid, c->mx, c->my, c->mz, cb, c->rec, c->gitems, item0, c->ntile[2],
              c->ntile[1], wmode, out, ldc, c0, caller_order);
   CS_HIP(c, hipGetLastError());
   return CS_OK;
@@ -272,15 +235,20 @@ int interp_tile_launch(cs_ctx* c, const float2* grid, int cb, int wmode, float2*
 
 // coil groups of at most cmax coils (3D: 8 planar coils of the 11^3 tile
 // take 85 KB of LDS, 12 take 128 KB) or 16 (2D); the group size is the chunk
-// split evenly
+// split evenly.  Variant 0 reads the grid in global memory (groups of 8).
 template <int NDIM>
-int interp_tile_dispatch(cs_ctx* c, const float2* grid, int cb, int wmode, float2* out,
-                         int ldc, int c0, int caller_order, int cmax) {
+int interp_dispatch(cs_ctx* c, const float2* grid, int cb, int item0, int nitems, int wmode,
+                    float2* out, int ldc, int c0, int caller_order) {
+  const bool tile = c->interp_cfg >= 1;
+  int cmax = c->interp_cfg == 2 ? 12 : (c->interp_cfg == 3 ? 4 : 8);
   if (NDIM == 2) cmax = 16;
   const int ng = (cb + cmax - 1) / cmax;
   const int cg = (cb + ng - 1) / ng;
-#define CS_ITILE(CG) \
-  return interp_tile_launch<NDIM, CG>(c, grid, cb, wmode, out, ldc, c0, caller_order)
+#define CS_ITILE(CG)                                                                        \
+  return tile ? interp_launch<NDIM, CG, true>(c, grid, cb, item0, nitems, wmode, out, ldc, \
+                                              c0, caller_order)                            \
+              : interp_launch<NDIM, CG, false>(c, grid, cb, item0, nitems, wmode, out,     \
+                                               ldc, c0, caller_order)
   if (cg <= 2) CS_ITILE(2);
   if (cg <= 4) CS_ITILE(4);
   if (cg <= 6) CS_ITILE(6);
@@ -296,6 +264,7 @@ constexpr int kSpreadBatch = 64;  // samples staged in LDS per step
 // (the products are formed once per sample in the staging, not by every
 // coil wave for every tap)
 constexpr int kSpreadRecPitch = 21;
+enum { SRC_VALS = 0, SRC_DATA = 1 };
 
 // One work-group = one work item (a contiguous range of the samples of one
 // tile, in sorted order) and one group of CG = NW * LPC * CW coils.  Lane l
@@ -306,10 +275,15 @@ constexpr int kSpreadRecPitch = 21;
 // distinct coils, and a wave issues its LDS operations in order, so the
 // summation order of every voxel is fixed.  The halo'd tile is written to
 // the item's slot; k_spread_merge sums the slots that cover each voxel.
-template <int NDIM, int NW, int CW>
-__global__ __launch_bounds__(64 * NW) void k_spread(
-    const float2* __restrict__ V, int cb, const SampleRec* __restrict__ rec,
-    const int4* __restrict__ items, int ntx, int nty, float2* __restrict__ P) {
+// Sample values come from `V`: with SRC_VALS row voff + (k - kbeg) of the
+// item group's values (cb coils per row); with SRC_DATA the caller's data
+// row orig (coils c0 .. at leading dimension ldc), scaled by sqrt(w)
+// (folded into the staged x weights).
+template <int NDIM, int NW, int CW, int SRC>
+__global__ __launch_bounds__(64 * NW) void k_spread_items(
+    const float2* __restrict__ V, int ldc, int c0, int cb, const SampleRec* __restrict__ rec,
+    const GridItem* __restrict__ items, int item0, int ntx, int nty,
+    float2* __restrict__ P) {
   using H = Halo<NDIM>;
   constexpr int NT = 64 * NW;
   constexpr int CG = NW * H::LPC * CW;
@@ -326,12 +300,10 @@ __global__ __launch_bounds__(64 * NW) void k_spread(
   __shared__ int s_rs[SB];  // run starts of the staged batch
   __shared__ int s_nr;
 
-  const int4 it = items[blockIdx.x];
-  const int tile = it.x, kbeg = it.y, kend = it.z, slot = it.w;
+  const GridItem it = items[item0 + blockIdx.x];
+  const int tile = it.tile, kbeg = it.kbeg, kend = it.kend, slot = it.slot;
   const int g = blockIdx.y, ng = gridDim.y;
   const int cg0 = g * CG, cga = min(CG, cb - cg0);
-  const int ix = tile % ntx, iy = (tile / ntx) % nty, iz = tile / (ntx * nty);
-  const int x0 = ix * H::TX, y0 = iy * H::TY, z0 = iz * H::TZ;
   // the wave index through readfirstlane: the compiler then knows it (and
   // all that depends only on it) to be uniform across the wave
   const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6),
@@ -350,18 +322,17 @@ __global__ __launch_bounds__(64 * NW) void k_spread(
 
   // staging, double-buffered through registers: thread t < SB fetches the
   // record of sample t of the batch; value e = t + j NT is (sample e / CG,
-  // group coil e % CG)
-  // (the loaded values are only consumed after the next barrier, so the
-  // loads stay in flight while the current batch is processed)
-  int pb[3] = {0, 0, 0};
-  float pw[12];
+  // group coil e % CG).  The loaded values are only consumed after the next
+  // barrier, so the loads stay in flight while the current batch is
+  // processed.
+  int pkey = 0;
+  float pw[12], psw = 1.f;
   float2 pv[VPT];
   auto prefetch = [&](int k0, int n) {
     if (tid < n) {
       const SampleRec& r = rec[k0 + tid];
-      pb[0] = r.bx;
-      pb[1] = r.by;
-      pb[2] = r.bz;
+      pkey = r.key;
+      psw = r.sw;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         pw[q] = r.wx[q];
@@ -372,8 +343,14 @@ __global__ __launch_bounds__(64 * NW) void k_spread(
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       const int e = tid + j * NT, s = e / CG, q = e - s * CG;
-      pv[j] = (s < n && q < cga) ? V[(long long)(k0 + s) * cb + cg0 + q]
-                                 : make_float2(0.f, 0.f);
+      float2 v = make_float2(0.f, 0.f);
+      if (s < n && q < cga) {
+        if constexpr (SRC == SRC_VALS)
+          v = V[(long long)(it.voff + k0 - kbeg + s) * cb + cg0 + q];
+        else
+          v = V[(long long)rec[k0 + s].orig * ldc + c0 + cg0 + q];
+      }
+      pv[j] = v;
     }
   };
   if (kbeg < kend) prefetch(kbeg, min(SB, kend - kbeg));
@@ -381,12 +358,13 @@ __global__ __launch_bounds__(64 * NW) void k_spread(
   for (int k0 = kbeg; k0 < kend; k0 += SB) {
     const int n = min(SB, kend - k0);
     __syncthreads();  // previous batch consumed (and accumulator zeroed)
-    const int pkey = (pb[0] - x0) | ((pb[1] - y0) << 8) | ((pb[2] - z0) << 16);
     if (tid < n) {
+      // x weights (times sqrt(w) for caller data), then wy[dy] wz[dz]
+      const float sx = SRC == SRC_DATA ? psw : 1.f;
       float* d = srec + tid * SRP;
       d[0] = __int_as_float(pkey);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) d[1 + q] = pw[q];
+      for (int q = 0; q < 4; ++q) d[1 + q] = pw[q] * sx;
 #pragma unroll
       for (int q = 0; q < 16; ++q)
         d[5 + q] = NDIM == 3 ? pw[4 + (q & 3)] * pw[8 + (q >> 2)] : pw[4 + (q & 3)];
@@ -456,6 +434,167 @@ __global__ __launch_bounds__(64 * NW) void k_spread(
   __syncthreads();
   // write-out: slot layout [slot][group][EXT][CG]; one thread per voxel
   // writes the group's CG coils of that voxel (contiguous)
+  float2* dst = P + ((size_t)slot * ng + g) * H::EXT * CG;
+  for (int e = tid; e < H::EXT; e += NT) {
+    const int lx = e % H::EX, ly = (e / H::EX) % H::EY, lz = e / (H::EX * H::EY);
+    const int a = lz * H::PZ + ly * H::PY + lx;
+    float2* d = dst + (size_t)e * CG;
+#pragma unroll
+    for (int q = 0; q < CG; ++q)
+      d[q] = make_float2(acc[(size_t)q * 2 * H::PLANE + a],
+                         acc[(size_t)q * 2 * H::PLANE + H::PLANE + a]);
+  }
+}
+
+// The 3D spreading of the normal operator with the sample values held in
+// vector registers instead of LDS: lane j of a wave keeps sample j's values
+// of the wave's CW coils, and each sample's values are broadcast to the
+// wave's lanes by v_readlane into scalar registers that enter the FMAs as
+// scalar operands.  Only the kernel weights go through LDS.  Summation
+// order as in k_spread_items (bit-identical results).
+template <int NW, int CW>
+__global__ __launch_bounds__(64 * NW) void k_spread_rl(
+    const float2* __restrict__ V, int /*ldc*/, int /*c0*/, int cb,
+    const SampleRec* __restrict__ rec,
+    const GridItem* __restrict__ items, int item0, int ntx, int nty,
+    float2* __restrict__ P) {
+  using H = Halo<3>;
+  constexpr int NT = 64 * NW;
+  constexpr int CG = NW * CW;
+  constexpr int SB = kSpreadBatch, SRP = kSpreadRecPitch;
+  extern __shared__ float lds[];
+  float* acc = lds;                               // [CG][2][PLANE]
+  float* srec = acc + (size_t)CG * 2 * H::PLANE;  // [SB][SRP]
+  __shared__ int s_rs[SB];
+  __shared__ int s_nr;
+
+  const GridItem it = items[item0 + blockIdx.x];
+  const int tile = it.tile, kbeg = it.kbeg, kend = it.kend, slot = it.slot;
+  const int g = blockIdx.y, ng = gridDim.y;
+  const int cg0 = g * CG, cga = min(CG, cb - cg0);
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6),
+            lane = tid & 63;
+  for (int i = tid; i < CG * 2 * H::PLANE; i += NT) acc[i] = 0.f;
+
+  const int dx = lane & 3, dy = (lane >> 2) & 3, dz = lane >> 4;
+  const int q0 = wave * CW;  // first group coil of this wave
+  const bool active = q0 < cga;
+  float2 racc[CW];
+#pragma unroll
+  for (int q = 0; q < CW; ++q) racc[q] = make_float2(0.f, 0.f);
+  int rkey = -1, raddr = 0;
+
+  // thread t < SB fetches the record of sample t of the next batch; lane j of
+  // every wave fetches sample j's values of the wave's coils, which pass
+  // through this wave's slice of LDS once per batch (so that no load is in
+  // flight while the loop below broadcasts them)
+  float* sval = srec + SB * SRP;  // [NW][CW][2][64]
+  int pkey = 0;
+  float pw[12];
+  float2 nv[CW], cv[CW];
+  auto prefetch = [&](int k0, int n) {
+    if (tid < n) {
+      const SampleRec& r = rec[k0 + tid];
+      pkey = r.key;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        pw[q] = r.wx[q];
+        pw[4 + q] = r.wy[q];
+        pw[8 + q] = r.wz[q];
+      }
+    }
+    const float2* vr = V + (long long)(it.voff + k0 - kbeg + lane) * cb + cg0 + q0;
+#pragma unroll
+    for (int q = 0; q < CW; ++q)
+      nv[q] = (lane < n && q0 + q < cga) ? vr[q] : make_float2(0.f, 0.f);
+  };
+  if (kbeg < kend) prefetch(kbeg, min(SB, kend - kbeg));
+
+  for (int k0 = kbeg; k0 < kend; k0 += SB) {
+    const int n = min(SB, kend - k0);
+    __syncthreads();  // previous batch consumed (and accumulator zeroed)
+    if (tid < n) {
+      float* d = srec + tid * SRP;
+      d[0] = __int_as_float(pkey);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) d[1 + q] = pw[q];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) d[5 + q] = pw[4 + (q & 3)] * pw[8 + (q >> 2)];
+    }
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+      sval[((wave * CW + q) * 2) * 64 + lane] = nv[q].x;
+      sval[((wave * CW + q) * 2 + 1) * 64 + lane] = nv[q].y;
+    }
+    if (tid < 64) {
+      const int prev = __shfl_up(pkey, 1);
+      const bool start = tid < n && pkey != (tid > 0 ? prev : rkey);
+      const unsigned long long mask = __ballot(start);
+      if (start) s_rs[__popcll(mask & ((1ull << tid) - 1ull))] = tid;
+      if (tid == 0) s_nr = __popcll(mask);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < CW; ++q)
+      cv[q] = make_float2(sval[((wave * CW + q) * 2) * 64 + lane],
+                          sval[((wave * CW + q) * 2 + 1) * 64 + lane]);
+    // lane j: key of sample j and start of run j of the batch (broadcast
+    // by v_readlane below instead of a LDS round trip per run)
+    const int vkey = __float_as_int(srec[lane * SRP]);
+    const int vrs = s_rs[lane];
+    if (k0 + SB < kend) prefetch(k0 + SB, min(SB, kend - k0 - SB));
+    // one sample of the current run (uniform s: the lane reads are
+    // broadcasts through scalar registers)
+    auto one = [&](int s) {
+      const float* d = srec + s * SRP;
+      const float w = d[1 + dx] * d[5 + dy + 4 * dz];
+#pragma unroll
+      for (int q = 0; q < CW; ++q) {
+        const float vr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cv[q].x), s));
+        const float vi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cv[q].y), s));
+        racc[q].x += w * vr;
+        racc[q].y += w * vi;
+      }
+    };
+    const int nr = active ? __builtin_amdgcn_readfirstlane(s_nr) : -1;
+    int s = 0;
+    for (int r = -1; r < nr; ++r) {
+      const int s1 = (r + 1 < nr) ? __builtin_amdgcn_readlane(vrs, r + 1) : n;
+      if (r >= 0) {
+        if (rkey >= 0) {
+#pragma unroll
+          for (int q = 0; q < CW; ++q) {
+            float* pl = acc + (size_t)(q0 + q) * 2 * H::PLANE + raddr;
+            pl[0] += racc[q].x;
+            pl[H::PLANE] += racc[q].y;
+            racc[q] = make_float2(0.f, 0.f);
+          }
+        }
+        rkey = __builtin_amdgcn_readlane(vkey, s);
+        const int lx = (rkey & 0xff) + dx, ly = ((rkey >> 8) & 0xff) + dy,
+                  lz = (rkey >> 16) + dz;
+        raddr = lz * H::PZ + ly * H::PY + lx;
+      }
+      // unrolled by hand (the broadcasts are convergent operations, which
+      // the compiler does not unroll at a run-time trip count)
+      for (; s + 4 <= s1; s += 4) {
+        one(s);
+        one(s + 1);
+        one(s + 2);
+        one(s + 3);
+      }
+      for (; s < s1; ++s) one(s);
+    }
+  }
+  if (rkey >= 0) {
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+      float* pl = acc + (size_t)(q0 + q) * 2 * H::PLANE + raddr;
+      pl[0] += racc[q].x;
+      pl[H::PLANE] += racc[q].y;
+    }
+  }
+  __syncthreads();
   float2* dst = P + ((size_t)slot * ng + g) * H::EXT * CG;
   for (int e = tid; e < H::EXT; e += NT) {
     const int lx = e % H::EX, ly = (e / H::EX) % H::EY, lz = e / (H::EX * H::EY);
@@ -546,67 +685,6 @@ __global__ __launch_bounds__(256) void k_spread_merge(
     if (c < cb) out[c] = acc[c];
 }
 
-__global__ void k_gather_samples(const float2* __restrict__ y, int ldc, int c0, int cb,
-                                 const SampleRec* __restrict__ rec, long long N,
-                                 float2* __restrict__ vals) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N * cb) return;
-  const long long j = i / cb;
-  const int c = (int)(i - j * cb);
-  const SampleRec& r = rec[j];
-  const float2 v = y[(long long)r.orig * ldc + c0 + c];
-  vals[i] = make_float2(v.x * r.sw, v.y * r.sw);
-}
-
-template <int NDIM>
-int interp_dispatch(cs_ctx* c, const float2* grid, int cb, int wmode, float2* out,
-                    int ldc, int c0, int caller_order) {
-  const long long N = c->N;
-  const int bs = 256;
-  const unsigned nb = (unsigned)((N + bs - 1) / bs);
-#define CS_INTERP(CBT)                                                                \
-  CS_KLAUNCH(c, K_INTERP, (k_interp<NDIM, CBT>), dim3(nb), dim3(bs), 0, c->stream, grid,   \
-                     c->mx, c->my, c->mz, cb, c->rec, N, wmode, out, ldc, c0,         \
-                     caller_order)
-  // even chunk sizes get an exact instantiation (vector loads); odd ones use
-  // the next odd bound with a runtime guard
-  switch (cb) {
-    case 2: CS_INTERP(2); break;
-    case 4: CS_INTERP(4); break;
-    case 6: CS_INTERP(6); break;
-    case 8: CS_INTERP(8); break;
-    case 10: CS_INTERP(10); break;
-    case 12: CS_INTERP(12); break;
-    case 14: CS_INTERP(14); break;
-    case 16: CS_INTERP(16); break;
-    default:
-      if (cb <= 3) CS_INTERP(3);
-      else if (cb <= 7) CS_INTERP(7);
-      else if (cb <= 11) CS_INTERP(11);
-      else CS_INTERP(15);
-  }
-#undef CS_INTERP
-  CS_HIP(c, hipGetLastError());
-  return CS_OK;
-}
-
-}  // namespace
-
-int launch_interp(cs_ctx* c, const float2* grid, int cb, int wmode, float2* out,
-                  int ldc, int c0, int caller_order) {
-  if (cb < 1 || cb > kCoilChunk) return fail(c, CS_EINVAL, "interp coil chunk");
-  if (c->N == 0) return CS_OK;
-  if (c->interp_cfg >= 1) {
-    const int cmax = c->interp_cfg == 1 ? 8 : (c->interp_cfg == 2 ? 12 : 4);
-    return c->ndim == 3
-               ? interp_tile_dispatch<3>(c, grid, cb, wmode, out, ldc, c0, caller_order, cmax)
-               : interp_tile_dispatch<2>(c, grid, cb, wmode, out, ldc, c0, caller_order, cmax);
-  }
-  return c->ndim == 3 ? interp_dispatch<3>(c, grid, cb, wmode, out, ldc, c0, caller_order)
-                      : interp_dispatch<2>(c, grid, cb, wmode, out, ldc, c0, caller_order);
-}
-
-namespace {
 template <int NDIM, int NW, int CW>
 constexpr int spread_cg() {
   return NW * Halo<NDIM>::LPC * CW;
@@ -620,24 +698,40 @@ size_t spread_lds_bytes() {
   return sizeof(float) * ((size_t)CG * 2 * H::PLANE + SR + (size_t)4 * kSpreadBatch * CG);
 }
 
-template <int NDIM, int NW, int CW>
-int spread_launch(cs_ctx* c, const float2* vals, int cb, float2* grid) {
+template <int NDIM, int NW, int CW, bool SV = false>
+int spread_items_launch(cs_ctx* c, int src, const float2* vals, int ldc, int c0, int cb,
+                        int item0, int nitems) {
   using H = Halo<NDIM>;
   constexpr int CG = spread_cg<NDIM, NW, CW>();
   const int ng = (cb + CG - 1) / CG;
   if ((size_t)c->n_items * ng * H::EXT * CG > c->partial_elems)
     return fail(c, CS_EINVAL, "spread partial buffer too small");
-  const size_t lds = spread_lds_bytes<NDIM, NW, CW>();
+  // the register-broadcast variant serves the 3D normal operator; 2D (four
+  // coil slots per wave) and the caller's data use the LDS-staged one
+  const bool rl = SV && NDIM == 3 && src == SRC_VALS;
+  const size_t lds = rl ? sizeof(float) * ((size_t)CG * 2 * H::PLANE +
+                                           kSpreadBatch * kSpreadRecPitch + CG * 2 * 64)
+                        : spread_lds_bytes<NDIM, NW, CW>();
   if (lds > 160 * 1024) return fail(c, CS_EINVAL, "spread tile does not fit in LDS");
-  if (c->n_items > 0) {
-    auto kern = k_spread<NDIM, NW, CW>;
-    if (lds > 64 * 1024)
-      CS_HIP(c, hipFuncSetAttribute((const void*)kern,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    CS_KLAUNCH(c, K_SPREAD, kern, dim3((unsigned)c->n_items, (unsigned)ng), dim3(64 * NW), lds,
-               c->stream, vals, cb, c->rec, c->items, c->ntile[2], c->ntile[1], c->partial);
-    CS_HIP(c, hipGetLastError());
-  }
+  if (nitems <= 0) return CS_OK;
+  auto kern = rl ? k_spread_rl<NW, CW>
+                 : (src == SRC_VALS ? k_spread_items<NDIM, NW, CW, SRC_VALS>
+                                    : k_spread_items<NDIM, NW, CW, SRC_DATA>);
+  if (lds > 64 * 1024)
+    CS_HIP(c, hipFuncSetAttribute((const void*)kern,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  CS_KLAUNCH(c, K_SPREAD, kern, dim3((unsigned)nitems, (unsigned)ng), dim3(64 * NW), lds,
+             c->stream, vals, ldc, c0, cb, c->rec, c->gitems, item0, c->ntile[2],
+             c->ntile[1], c->partial);
+  CS_HIP(c, hipGetLastError());
+  return CS_OK;
+}
+
+template <int NDIM, int NW, int CW>
+int merge_launch(cs_ctx* c, int cb, float2* grid) {
+  using H = Halo<NDIM>;
+  constexpr int CG = spread_cg<NDIM, NW, CW>();
+  const int ng = (cb + CG - 1) / CG;
   constexpr long long TV = (long long)H::TX * H::TY * H::TZ;
   const long long blocks = c->ntiles * ((TV + 255) / 256);
   if (blocks > 0x7fffffffLL) return fail(c, CS_EINVAL, "spread merge grid too large");
@@ -649,29 +743,43 @@ int spread_launch(cs_ctx* c, const float2* vals, int cb, float2* grid) {
 }
 
 // work-group shapes (waves NW, coils per lane CW); the coils of a group are
-// NW * CW (3D) or 4 NW CW (2D, four coil slots of 16 taps per wave)
+// NW * CW (3D) or 4 NW CW (2D, four coil slots of 16 taps per wave).
+// `what`: 0 spread a range of items, 1 merge every slot into the grid.
 template <int NDIM>
-int spread_dispatch(cs_ctx* c, const float2* vals, int cb, float2* grid) {
+int spread_dispatch(cs_ctx* c, int what, int src, const float2* vals, int ldc, int c0, int cb,
+                    int item0, int nitems, float2* grid) {
+#define CS_SHAPE(NW, CW)                                                                   \
+  return what == 0 ? spread_items_launch<NDIM, NW, CW>(c, src, vals, ldc, c0, cb, item0,  \
+                                                       nitems)                             \
+                   : merge_launch<NDIM, NW, CW>(c, cb, grid)
+#define CS_SHAPE_SV(NW, CW)                                                                \
+  return what == 0 ? spread_items_launch<NDIM, NW, CW, true>(c, src, vals, ldc, c0, cb,   \
+                                                             item0, nitems)                \
+                   : merge_launch<NDIM, NW, CW>(c, cb, grid)
   switch (c->spread_cfg) {
-    case 1: return spread_launch<NDIM, 2, 2>(c, vals, cb, grid);
-    case 2: return spread_launch<NDIM, 2, 1>(c, vals, cb, grid);
-    case 3: return spread_launch<NDIM, 1, 4>(c, vals, cb, grid);
-    case 4: return spread_launch<NDIM, 4, 2>(c, vals, cb, grid);
-    case 5: return spread_launch<NDIM, 1, 3>(c, vals, cb, grid);
+    case 0: CS_SHAPE_SV(4, 1);
+    case 7: CS_SHAPE(4, 1);
+    case 1: CS_SHAPE(2, 2);
+    case 2: CS_SHAPE(2, 1);
+    case 3: CS_SHAPE(1, 4);
+    case 4: CS_SHAPE(4, 2);
+    case 5: CS_SHAPE(1, 3);
     case 6:
       // all coils of the chunk in one work-group where the LDS allows (one
       // wave per coil), so every sample is staged once
       if constexpr (NDIM == 3) {
-        if (cb <= 4) return spread_launch<NDIM, 4, 1>(c, vals, cb, grid);
-        if (cb <= 6) return spread_launch<NDIM, 6, 1>(c, vals, cb, grid);
-        if (cb <= 8) return spread_launch<NDIM, 8, 1>(c, vals, cb, grid);
-        if (cb <= 12) return spread_launch<NDIM, 12, 1>(c, vals, cb, grid);
-        return spread_launch<NDIM, 8, 1>(c, vals, cb, grid);
+        if (cb <= 4) CS_SHAPE(4, 1);
+        if (cb <= 6) CS_SHAPE(6, 1);
+        if (cb <= 8) CS_SHAPE(8, 1);
+        if (cb <= 12) CS_SHAPE(12, 1);
+        CS_SHAPE(8, 1);
       } else {
-        return spread_launch<NDIM, 4, 1>(c, vals, cb, grid);
+        CS_SHAPE(4, 1);
       }
-    default: return spread_launch<NDIM, 4, 1>(c, vals, cb, grid);
+    default: CS_SHAPE_SV(4, 1);
   }
+#undef CS_SHAPE
+#undef CS_SHAPE_SV
 }
 
 // largest coil-group size over the shapes above, for the partial buffer
@@ -682,23 +790,48 @@ int spread_max_group_elems(int ndim) {
   for (int cg : cgs) best = std::max(best, ((kCoilChunk + cg - 1) / cg) * cg);
   return best;
 }
-}  // namespace
 
-int launch_spread(cs_ctx* c, const float2* vals, int cb, float2* grid) {
-  if (cb < 1 || cb > kCoilChunk) return fail(c, CS_EINVAL, "spread coil chunk");
-  return c->ndim == 3 ? spread_dispatch<3>(c, vals, cb, grid)
-                      : spread_dispatch<2>(c, vals, cb, grid);
+int spread_items(cs_ctx* c, int src, const float2* vals, int ldc, int c0, int cb, int item0,
+                 int nitems) {
+  return c->ndim == 3
+             ? spread_dispatch<3>(c, 0, src, vals, ldc, c0, cb, item0, nitems, nullptr)
+             : spread_dispatch<2>(c, 0, src, vals, ldc, c0, cb, item0, nitems, nullptr);
 }
 
-int launch_gather_samples(cs_ctx* c, const float2* y, int ldc, int c0, int cb,
-                          float2* vals) {
-  const long long n = c->N * cb;
-  if (n == 0) return CS_OK;
-  const int bs = 256;
-  CS_KLAUNCH(c, K_GATHER, k_gather_samples, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0,
-                     c->stream, y, ldc, c0, cb, c->rec, c->N, vals);
-  CS_HIP(c, hipGetLastError());
-  return CS_OK;
+int merge_slots(cs_ctx* c, int cb, float2* grid) {
+  return c->ndim == 3 ? spread_dispatch<3>(c, 1, 0, nullptr, 0, 0, cb, 0, 0, grid)
+                      : spread_dispatch<2>(c, 1, 0, nullptr, 0, 0, cb, 0, 0, grid);
+}
+
+int interp_items(cs_ctx* c, const float2* grid, int cb, int item0, int nitems, int wmode,
+                 float2* out, int ldc, int c0, int caller_order) {
+  return c->ndim == 3 ? interp_dispatch<3>(c, grid, cb, item0, nitems, wmode, out, ldc, c0,
+                                           caller_order)
+                      : interp_dispatch<2>(c, grid, cb, item0, nitems, wmode, out, ldc, c0,
+                                           caller_order);
+}
+
+}  // namespace
+
+int grid_normal(cs_ctx* c, const float2* grid, int cb, float2* out_grid) {
+  if (cb < 1 || cb > kCoilChunk) return fail(c, CS_EINVAL, "gridding coil chunk");
+  for (size_t g = 0; g + 1 < c->group_off.size(); ++g) {
+    const int i0 = c->group_off[g], i1 = c->group_off[g + 1];
+    CS_TRY(interp_items(c, grid, cb, i0, i1 - i0, W_FULL, c->vbuf, cb, 0, 0));
+    CS_TRY(spread_items(c, SRC_VALS, c->vbuf, cb, 0, cb, i0, i1 - i0));
+  }
+  return merge_slots(c, cb, out_grid);
+}
+
+int grid_interp(cs_ctx* c, const float2* grid, int cb, float2* y, int ldc, int c0) {
+  if (cb < 1 || cb > kCoilChunk) return fail(c, CS_EINVAL, "gridding coil chunk");
+  return interp_items(c, grid, cb, 0, (int)c->n_items, W_SQRT, y, ldc, c0, 1);
+}
+
+int grid_spread_data(cs_ctx* c, const float2* y, int ldc, int c0, int cb, float2* out_grid) {
+  if (cb < 1 || cb > kCoilChunk) return fail(c, CS_EINVAL, "gridding coil chunk");
+  CS_TRY(spread_items(c, SRC_DATA, y, ldc, c0, cb, 0, (int)c->n_items));
+  return merge_slots(c, cb, out_grid);
 }
 
 int setup_noncart(cs_ctx* c, const float* coords_dev, const float* dcf_dev) {
@@ -731,9 +864,15 @@ int setup_noncart(cs_ctx* c, const float* coords_dev, const float* dcf_dev) {
   c->spread_cfg = cfg ? std::atoi(cfg) : 0;
   const char* icfg = std::getenv("CS_INTERP_CFG");
   c->interp_cfg = icfg ? std::atoi(icfg) : 1;
+  // samples per item group of the normal operator (CS_GROUP_SAMPLES in the
+  // environment; at least one work item)
+  const char* gcfg = std::getenv("CS_GROUP_SAMPLES");
+  long long group_cap = gcfg ? std::atoll(gcfg) : kGroupSamples;
+  group_cap = std::max(group_cap, 2048LL);
   for (int a = 0; a < 3; ++a) c->ntile[a] = (m[a] + c->tile[a] - 1) / c->tile[a];
   c->ntiles = (long long)c->ntile[0] * c->ntile[1] * c->ntile[2];
 
+  // per sample: first tap per axis (wrapped), its tile, and the record
   std::vector<SampleRec> rec(N);
   std::vector<unsigned long long> key(N);
   for (long long i = 0; i < N; ++i) {
@@ -752,25 +891,22 @@ int setup_noncart(cs_ctx* c, const float* coords_dev, const float* dcf_dev) {
       if (bw < 0) bw += m[a];
       base[a] = (int)bw;
     }
-    if (nd == 2) {
-      r.wz[0] = 1.f;
-      base[0] = 0;
-    }
-    r.bz = base[0]; r.by = base[1]; r.bx = base[2];
+    if (nd == 2) r.wz[0] = 1.f;
+    r.key = (base[2] % c->tile[2]) | ((base[1] % c->tile[1]) << 8) |
+            ((base[0] % c->tile[0]) << 16);
     r.orig = (int)i;
     const double w = dcf_dev ? (double)dcf[i] : 1.0;
     r.w = (float)w;
     r.sw = (float)std::sqrt(w);
     rec[i] = r;
-    const long long t = ((long long)(r.bz / c->tile[0]) * c->ntile[1] + r.by / c->tile[1]) *
-                            c->ntile[2] + r.bx / c->tile[2];
-    const long long vox = ((long long)r.bz * m[1] + r.by) * m[2] + r.bx;
+    const long long t = ((long long)(base[0] / c->tile[0]) * c->ntile[1] + base[1] / c->tile[1]) *
+                            c->ntile[2] + base[2] / c->tile[2];
+    const long long vox = ((long long)base[0] * m[1] + base[1]) * m[2] + base[2];
     key[i] = ((unsigned long long)t << 40) | (unsigned long long)vox;
   }
-  std::vector<long long> order(N);
-  std::iota(order.begin(), order.end(), 0LL);
-  std::stable_sort(order.begin(), order.end(),
-                   [&](long long a, long long b) { return key[a] < key[b]; });
+  std::vector<int> order(N);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
   std::vector<SampleRec> srec(N);
   for (long long j = 0; j < N; ++j) srec[j] = rec[order[j]];
 
@@ -787,26 +923,61 @@ int setup_noncart(cs_ctx* c, const float* coords_dev, const float* dcf_dev) {
     CS_HIP(c, hipMemcpy(c->dcf_orig, dcf.data(), sizeof(float) * N, hipMemcpyHostToDevice));
   }
 
-  // spread work items: each tile's samples in chunks of at most `chunk`; the
-  // slot of an item is its index in tile order, so the slots of tile t are
+  // work items: each tile's samples in chunks of at most `chunk`; the slot of
+  // an item is its index in tile order, so the slots of tile t are
   // item_off[t] .. item_off[t + 1]
   const long long chunk = 2048;
-  std::vector<int4> items;
+  std::vector<GridItem> items;
   std::vector<int> ioff(c->ntiles + 1, 0);
   for (long long t = 0; t < c->ntiles; ++t) {
     for (long long k = toff[t]; k < toff[t + 1]; k += chunk) {
-      const int slot = (int)items.size();
-      items.push_back(make_int4((int)t, (int)k, (int)std::min(toff[t + 1], k + chunk), slot));
+      GridItem g{};
+      g.tile = (int)t;
+      g.kbeg = (int)k;
+      g.kend = (int)std::min(toff[t + 1], k + chunk);
+      g.slot = (int)items.size();
+      items.push_back(g);
     }
     ioff[t + 1] = (int)items.size();
   }
-  // heavy items first so that the long ones start early
-  std::stable_sort(items.begin(), items.end(),
-                   [](const int4& a, const int4& b) { return (a.z - a.y) > (b.z - b.y); });
-  c->n_items = (long long)items.size();
-  CS_HIP(c, hipMalloc(&c->items, sizeof(int4) * std::max<size_t>(1, items.size())));
-  if (!items.empty())
-    CS_HIP(c, hipMemcpy(c->items, items.data(), sizeof(int4) * items.size(),
+  // item groups of the normal operator: at most group_cap samples each,
+  // whose values (one row of <= kCoilChunk coils per sample) go to the value
+  // buffer at the item's offset voff.  Items are dealt, heaviest first,
+  // round-robin to the groups, and each group runs its heaviest items first
+  // so that the long ones start early.
+  std::stable_sort(items.begin(), items.end(), [](const GridItem& a, const GridItem& b) {
+    return (a.kend - a.kbeg) > (b.kend - b.kbeg);
+  });
+  const long long ngroups = std::max(1LL, (N + group_cap - 1) / group_cap);
+  std::vector<std::vector<GridItem>> groups(ngroups);
+  std::vector<long long> gsize(ngroups, 0);
+  for (const GridItem& it : items) {
+    // the lightest group that still has room (dealing in order keeps them level)
+    long long best = -1;
+    for (long long g = 0; g < ngroups; ++g)
+      if (gsize[g] + (it.kend - it.kbeg) <= group_cap && (best < 0 || gsize[g] < gsize[best]))
+        best = g;
+    if (best < 0) {
+      best = (long long)groups.size();
+      groups.emplace_back();
+      gsize.push_back(0);
+    }
+    GridItem g = it;
+    g.voff = (int)gsize[best];
+    gsize[best] += it.kend - it.kbeg;
+    groups[best].push_back(g);
+  }
+  std::vector<GridItem> ordered;
+  c->group_off.assign(1, 0);
+  for (auto& g : groups) {
+    if (g.empty()) continue;
+    ordered.insert(ordered.end(), g.begin(), g.end());
+    c->group_off.push_back((int)ordered.size());
+  }
+  c->n_items = (long long)ordered.size();
+  CS_HIP(c, hipMalloc(&c->gitems, sizeof(GridItem) * std::max<size_t>(1, ordered.size())));
+  if (!ordered.empty())
+    CS_HIP(c, hipMemcpy(c->gitems, ordered.data(), sizeof(GridItem) * ordered.size(),
                         hipMemcpyHostToDevice));
   CS_HIP(c, hipMalloc(&c->item_off, sizeof(int) * ioff.size()));
   CS_HIP(c, hipMemcpy(c->item_off, ioff.data(), sizeof(int) * ioff.size(),
@@ -814,6 +985,13 @@ int setup_noncart(cs_ctx* c, const float* coords_dev, const float* dcf_dev) {
   const size_t ext = nd == 3 ? (size_t)Halo<3>::EXT : (size_t)Halo<2>::EXT;
   c->partial_elems = std::max<size_t>(1, (size_t)c->n_items * ext * spread_max_group_elems(nd));
   CS_HIP(c, hipMalloc(&c->partial, sizeof(float2) * c->partial_elems));
+  // values of the largest item group, kCoilChunk coils per sample
+  long long gmax = 1;
+  for (long long g : gsize) gmax = std::max(gmax, g);
+  // padded by kCoilChunk coils: the scalar-value spreading reads whole runs
+  // of a wave's coils, which run past the last row when a chunk is partial
+  c->vbuf_pad = kCoilChunk;
+  CS_HIP(c, hipMalloc(&c->vbuf, sizeof(float2) * ((size_t)gmax * kCoilChunk + kCoilChunk)));
   return CS_OK;
 }
 

@@ -404,6 +404,20 @@ int coil_mix(cs_ctx* c, const float2* in, int in_ldc, int in_c0, int cin, const 
                        out_scale);
 }
 
+// fragment buffer and pinned staging ring sized for the largest mixing
+// matrix (64 x 64), so that coil mixing never allocates
+int coil_mix_reserve(cs_ctx* c) {
+  const size_t bytes = (size_t)3 * 8 * 8 * 64 * 4 * sizeof(unsigned short);
+  CS_HIP(c, hipMalloc(&c->mixB, bytes));
+  c->mixB_bytes = bytes;
+  for (int k = 0; k < cs_ctx::kStage; ++k) {
+    CS_HIP(c, hipHostMalloc(&c->stage[k], bytes, 0));
+    c->stage_bytes[k] = bytes;
+    CS_HIP(c, hipEventCreateWithFlags(&c->stage_ev[k], hipEventDisableTiming));
+  }
+  return CS_OK;
+}
+
 int coil_mix_rows(cs_ctx* c, long long rows, const float2* in, int in_ldc, int in_c0, int cin,
                   const double* M, int cout, float2* out, int out_ldc, int out_c0,
                   float out_scale) {
@@ -446,25 +460,13 @@ int coil_mix_rows(cs_ctx* c, long long rows, const float2* in, int in_ldc, int i
           frag[2 * term + base] = lo;
         }
   const size_t bytes = frag.size() * sizeof(unsigned short);
-  if (bytes > c->mixB_bytes) {
-    if (c->mixB) CS_HIP(c, hipFree(c->mixB));
-    c->mixB = nullptr;
-    CS_HIP(c, hipMalloc(&c->mixB, bytes));
-    c->mixB_bytes = bytes;
-  }
+  if (bytes > c->mixB_bytes || bytes > c->stage_bytes[c->stage_next])
+    return fail(c, CS_EINVAL, "coil_mix: fragments exceed the reserved buffers");
   // stage through a pinned ring slot whose previous copy has completed (no
   // stream-wide synchronisation)
   const int k = c->stage_next;
   c->stage_next = (k + 1) % cs_ctx::kStage;
-  if (c->stage_ev[k]) CS_HIP(c, hipEventSynchronize(c->stage_ev[k]));
-  else CS_HIP(c, hipEventCreateWithFlags(&c->stage_ev[k], hipEventDisableTiming));
-  if (bytes > c->stage_bytes[k]) {
-    if (c->stage[k]) CS_HIP(c, hipHostFree(c->stage[k]));
-    c->stage[k] = nullptr;
-    c->stage_bytes[k] = 0;
-    CS_HIP(c, hipHostMalloc(&c->stage[k], bytes, 0));
-    c->stage_bytes[k] = bytes;
-  }
+  CS_HIP(c, hipEventSynchronize(c->stage_ev[k]));
   std::memcpy(c->stage[k], frag.data(), bytes);
   CS_HIP(c, hipMemcpyAsync(c->mixB, c->stage[k], bytes, hipMemcpyHostToDevice, c->stream));
   CS_HIP(c, hipEventRecord(c->stage_ev[k], c->stream));

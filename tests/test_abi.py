@@ -95,3 +95,27 @@ def test_binding_refuses_host_tensors_and_wrong_dtypes():
         binding._need(x.to(torch.complex128), torch.complex64, (4, 4), "x")
     with pytest.raises(TypeError, match="torch tensor"):
         binding._need(x.numpy(), torch.complex64, (4, 4), "x")
+
+
+def test_workspace_size_and_null_contexts_without_gpu():
+    # cs_workspace_size validates the geometry like cs_create and needs no
+    # device; the injection and reservation calls reject a null context
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    from paper_2305_06482_amd import binding
+    lib = binding.load()
+    nb = binding.workspace_size((64, 48), 8, "cart")
+    # two grids of 16 coils, 12 images, maps-sized virtual / sketched maps ...
+    D = 64 * 48
+    assert nb >= 8 * D * (2 * 16 + 12 + 2 * 8)
+    assert nb % 256 == 0
+    nc = binding.workspace_size((16, 16, 16), 4, "noncart", nsamp=1000)
+    assert nc >= 8 * 20 ** 3 * 16 * 2  # two oversampled grids (sigma 1.25)
+    g = binding._geom((64, 48), 0, "cart")
+    out = ctypes.c_size_t()
+    assert lib.cs_workspace_size(ctypes.byref(g), ctypes.byref(out)) == -1
+    assert b"ncoil" in lib.cs_last_error(None)
+    assert lib.cs_set_basis(None, None, None) == -1
+    assert lib.cs_set_sketch(None, 1, 1, None) == -1
+    assert lib.cs_reserve_recon(None, 0, 0) == -1
+    assert lib.cs_create_ws(ctypes.byref(g), None, 0, None, ctypes.byref(ctypes.c_void_p())) == -1
