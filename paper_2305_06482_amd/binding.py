@@ -19,7 +19,8 @@ from dataclasses import dataclass, field
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcoilsketch.so")
+# COILSKETCH_LIB in the environment names another build of the library
+LIB_PATH = os.environ.get("COILSKETCH_LIB") or os.path.join(_HERE, "libcoilsketch.so")
 
 CS_CART = 0
 CS_NONCART = 1

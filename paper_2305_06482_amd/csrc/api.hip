@@ -805,6 +805,8 @@ int cs_set_operator(cs_ctx* c, const void* maps, const uint8_t* mask, const floa
   if (!c) return CS_EINVAL;
   if (!maps) return fail(c, CS_EINVAL, "maps is null");
   CS_HIP(c, hipStreamSynchronize(c->stream));
+  // the context has no operator until this call succeeds
+  c->have_op = false;
   c->maps = (const float2*)maps;
   c->have_U = false;
   c->have_b = false;

@@ -37,8 +37,11 @@
 namespace cs {
 
 // I0 by its power series sum (x^2/4)^k / (k!)^2 (converges for all x; the
-// argument here is at most beta ~ 7).
-double kb_i0(double x) {
+// argument here is at most beta ~ 7).  Host and device evaluate it (and the
+// kernel below) with the same operations and no contraction into FMAs, so the
+// set-up's weights do not depend on where they are computed.
+__host__ __device__ double kb_i0_hd(double x) {
+#pragma clang fp contract(off)
   const double q = 0.25 * x * x;
   double term = 1.0, sum = 1.0;
   for (int k = 1; k < 200; ++k) {
@@ -48,6 +51,8 @@ double kb_i0(double x) {
   }
   return sum;
 }
+
+double kb_i0(double x) { return kb_i0_hd(x); }
 
 // Fourier transform of the KB kernel I0(beta sqrt(1 - (2t/W)^2)) on |t| <= W/2
 // at frequency nu: W sinh(sqrt(beta^2 - (pi W nu)^2)) / sqrt(...).
@@ -66,9 +71,10 @@ double kb_ft(double nu, double W, double beta) {
 
 namespace {
 
-double kb_kernel(double t, double W, double beta) {
+__host__ __device__ double kb_kernel(double t, double W, double beta) {
+#pragma clang fp contract(off)
   const double z = 1.0 - (2.0 * t / W) * (2.0 * t / W);
-  return z >= 0 ? kb_i0(beta * std::sqrt(z)) : 0.0;
+  return z >= 0 ? kb_i0_hd(beta * sqrt(z)) : 0.0;
 }
 
 __device__ __forceinline__ float sel4(const float* w, int i) {
@@ -834,24 +840,146 @@ int grid_spread_data(cs_ctx* c, const float2* y, int ldc, int c0, int cb, float2
   return merge_slots(c, cb, out_grid);
 }
 
+namespace {
+
+// ---- set-up of the trajectory on the GPU ------------------------------------
+
+struct SetupGeom {
+  int nd;
+  int n[3], m[3], T[3], nt[3];  // image, grid, tile size, tiles per axis (z, y, x)
+  double beta;
+};
+
+// One thread per sample (caller order): checks the coordinates and w, forms
+// the record (first tap per axis relative to its tile, w, sqrt(w), caller
+// index, kernel weights) and the sort key (tile, first tap in the tile) in
+// the high 32 bits above the caller index, so that sorting the keys is a
+// stable sort of the samples by tile and first tap.  err bit 1: a
+// coordinate outside [-n/2, n/2); bit 2: w < 0 or NaN.
+__global__ void k_setup_samples(const float* __restrict__ coords, const float* __restrict__ dcf,
+                                long long N, SetupGeom g, SampleRec* __restrict__ rec,
+                                unsigned long long* __restrict__ keys, int* __restrict__ err) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  SampleRec r{};
+  int base[3] = {0, 0, 0};
+  float* wts[3] = {r.wz, r.wy, r.wx};
+  bool bad = false;
+  for (int a = 3 - g.nd; a < 3; ++a) {
+    const double k = coords[i * g.nd + (2 - a)];
+    if (!(k >= -0.5 * g.n[a] && k < 0.5 * g.n[a])) {
+      bad = true;
+      continue;
+    }
+    const double u = k * (double)g.m[a] / (double)g.n[a];
+    const double f = floor(u);
+    const long long b = (long long)f - 1;
+    for (int j = 0; j < 4; ++j) wts[a][j] = (float)kb_kernel(u - (double)(b + j), 4.0, g.beta);
+    long long bw = b % g.m[a];
+    if (bw < 0) bw += g.m[a];
+    base[a] = (int)bw;
+  }
+  if (bad) atomicOr(err, 1);
+  if (g.nd == 2) r.wz[0] = 1.f;
+  const int lz = base[0] % g.T[0], ly = base[1] % g.T[1], lx = base[2] % g.T[2];
+  r.key = lx | (ly << 8) | (lz << 16);
+  r.orig = (int)i;
+  const double w = dcf ? (double)dcf[i] : 1.0;
+  if (!(w >= 0)) atomicOr(err, 2);
+  r.w = (float)w;
+  r.sw = (float)sqrt(w >= 0 ? w : 0.0);
+  rec[i] = r;
+  const unsigned long long t =
+      ((unsigned long long)(base[0] / g.T[0]) * g.nt[1] + base[1] / g.T[1]) * g.nt[2] +
+      base[2] / g.T[2];
+  const unsigned long long tv = (unsigned long long)g.T[0] * g.T[1] * g.T[2];
+  const unsigned long long k32 = t * tv + (unsigned long long)((lz * g.T[1] + ly) * g.T[2] + lx);
+  keys[i] = (k32 << 32) | (unsigned long long)i;
+}
+
+__global__ void k_fill_keys(unsigned long long* keys, long long from, long long to) {
+  const long long i = from + (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < to) keys[i] = ~0ull;
+}
+
+// Bitonic sort of a power-of-two array of 64-bit keys, ascending.  Stage k
+// merges runs of length k; step j compares elements j apart (direction by
+// bit k of the index).  Steps with j >= 2048 run one pass over the array
+// each; the steps j <= 1024 of a stage run in LDS, 2048 keys per block.
+constexpr int kSortBlock = 2048;
+
+__global__ __launch_bounds__(1024) void k_bitonic_local(unsigned long long* a, long long k0,
+                                                        long long k1) {
+  __shared__ unsigned long long s[kSortBlock];
+  const long long base = (long long)blockIdx.x * kSortBlock;
+  const int tid = threadIdx.x;
+  s[tid] = a[base + tid];
+  s[tid + 1024] = a[base + tid + 1024];
+  __syncthreads();
+  // stages k0 .. k1 (powers of two); for k > 2048 only its steps j <= 1024
+  for (long long k = k0; k <= k1; k <<= 1) {
+    for (int j = (int)(k / 2 < 1024 ? k / 2 : 1024); j > 0; j >>= 1) {
+      const int i = 2 * tid - (tid & (j - 1));
+      const bool asc = ((base + i) & k) == 0;
+      const unsigned long long x = s[i], y = s[i + j];
+      if ((x > y) == asc) {
+        s[i] = y;
+        s[i + j] = x;
+      }
+      __syncthreads();
+    }
+  }
+  a[base + tid] = s[tid];
+  a[base + tid + 1024] = s[tid + 1024];
+}
+
+__global__ void k_bitonic_global(unsigned long long* a, long long n, long long j, long long k) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n / 2) return;
+  const long long i = 2 * t - (t & (j - 1));
+  const bool asc = (i & k) == 0;
+  const unsigned long long x = a[i], y = a[i + j];
+  if ((x > y) == asc) {
+    a[i] = y;
+    a[i + j] = x;
+  }
+}
+
+// sorted record j = record of the sample in the low half of sorted key j
+__global__ void k_gather_sorted(const unsigned long long* __restrict__ keys,
+                                const SampleRec* __restrict__ rec, long long N,
+                                SampleRec* __restrict__ out) {
+  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < N) out[j] = rec[keys[j] & 0xffffffffull];
+}
+
+// toff[t] = first sorted sample of tile t or later (lower bound of t * TV in
+// the keys' high halves); toff[ntiles] = N
+__global__ void k_tile_offsets(const unsigned long long* __restrict__ keys, long long N,
+                               long long ntiles, unsigned long long tv, long long* toff) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > ntiles) return;
+  const unsigned long long want = (unsigned long long)t * tv;
+  long long lo = 0, hi = N;
+  while (lo < hi) {
+    const long long mid = (lo + hi) / 2;
+    if ((keys[mid] >> 32) < want) lo = mid + 1;
+    else hi = mid;
+  }
+  toff[t] = lo;
+}
+
+unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
 int setup_noncart(cs_ctx* c, const float* coords_dev, const float* dcf_dev) {
   const long long N = c->N;
   const int nd = c->ndim;
   if (N > 0x7fffffffLL) return fail(c, CS_EINVAL, "more than 2^31 - 1 samples");
-  std::vector<float> coords((size_t)N * nd), dcf;
-  if (N > 0)
-    CS_HIP(c, hipMemcpy(coords.data(), coords_dev, sizeof(float) * N * nd,
-                        hipMemcpyDeviceToHost));
   if (N == 0) dcf_dev = nullptr;  // empty trajectory: the zero operator
-  if (dcf_dev) {
-    dcf.resize(N);
-    CS_HIP(c, hipMemcpy(dcf.data(), dcf_dev, sizeof(float) * N, hipMemcpyDeviceToHost));
-    for (long long i = 0; i < N; ++i)
-      if (!(dcf[i] >= 0.f)) return fail(c, CS_EINVAL, "density compensation must be >= 0");
-  }
   const int n[3] = {c->nz, c->ny, c->nx};
   const int m[3] = {c->mz, c->my, c->mx};
-  const double W = 4.0, beta = c->beta;
 
   // spread tiles: 8x8x8 (3D) or 16x16 (2D) voxels; the work-group shape is
   // a tuning knob (CS_SPREAD_CFG in the environment, see spread_dispatch)
@@ -871,56 +999,79 @@ int setup_noncart(cs_ctx* c, const float* coords_dev, const float* dcf_dev) {
   group_cap = std::max(group_cap, 2048LL);
   for (int a = 0; a < 3; ++a) c->ntile[a] = (m[a] + c->tile[a] - 1) / c->tile[a];
   c->ntiles = (long long)c->ntile[0] * c->ntile[1] * c->ntile[2];
+  const unsigned long long tv = (unsigned long long)c->tile[0] * c->tile[1] * c->tile[2];
+  if ((unsigned long long)c->ntiles * tv >= (1ull << 32))
+    return fail(c, CS_EUNSUPPORTED, "NUFFT grid too large for the 32-bit sort keys");
 
-  // per sample: first tap per axis (wrapped), its tile, and the record
-  std::vector<SampleRec> rec(N);
-  std::vector<unsigned long long> key(N);
-  for (long long i = 0; i < N; ++i) {
-    SampleRec r{};
-    int base[3] = {0, 0, 0};
-    float* wts[3] = {r.wz, r.wy, r.wx};
-    for (int a = 3 - nd; a < 3; ++a) {
-      const double k = coords[(size_t)i * nd + (2 - a)];
-      if (!(k >= -0.5 * n[a] && k < 0.5 * n[a]))
-        return fail(c, CS_EINVAL, "coordinate outside [-n/2, n/2)");
-      const double u = k * (double)m[a] / (double)n[a];
-      const double f = std::floor(u);
-      const long long b = (long long)f - 1;
-      for (int j = 0; j < 4; ++j) wts[a][j] = (float)kb_kernel(u - (double)(b + j), W, beta);
-      long long bw = b % m[a];
-      if (bw < 0) bw += m[a];
-      base[a] = (int)bw;
-    }
-    if (nd == 2) r.wz[0] = 1.f;
-    r.key = (base[2] % c->tile[2]) | ((base[1] % c->tile[1]) << 8) |
-            ((base[0] % c->tile[0]) << 16);
-    r.orig = (int)i;
-    const double w = dcf_dev ? (double)dcf[i] : 1.0;
-    r.w = (float)w;
-    r.sw = (float)std::sqrt(w);
-    rec[i] = r;
-    const long long t = ((long long)(base[0] / c->tile[0]) * c->ntile[1] + base[1] / c->tile[1]) *
-                            c->ntile[2] + base[2] / c->tile[2];
-    const long long vox = ((long long)base[0] * m[1] + base[1]) * m[2] + base[2];
-    key[i] = ((unsigned long long)t << 40) | (unsigned long long)vox;
-  }
-  std::vector<int> order(N);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
-  std::vector<SampleRec> srec(N);
-  for (long long j = 0; j < N; ++j) srec[j] = rec[order[j]];
-
-  // samples per tile (each sample belongs to the tile of its first tap)
-  std::vector<long long> toff(c->ntiles + 1, 0);
-  for (long long j = 0; j < N; ++j) toff[(key[order[j]] >> 40) + 1]++;
-  for (long long t = 0; t < c->ntiles; ++t) toff[t + 1] += toff[t];
-
+  // records, keys, bitonic sort (the key's low half, the caller index, makes
+  // it stable), sorted records and tile offsets, all on the GPU
   CS_HIP(c, hipMalloc(&c->rec, sizeof(SampleRec) * std::max(1LL, N)));
-  if (N > 0)
-    CS_HIP(c, hipMemcpy(c->rec, srec.data(), sizeof(SampleRec) * N, hipMemcpyHostToDevice));
+  std::vector<long long> toff(c->ntiles + 1, 0);
+  if (N > 0) {
+    long long np = kSortBlock;
+    while (np < N) np *= 2;
+    SampleRec* rec_in = nullptr;
+    unsigned long long* keys = nullptr;
+    long long* toff_dev = nullptr;
+    int* err_dev = nullptr;
+    auto release = [&]() {
+      if (rec_in) (void)hipFree(rec_in);
+      if (keys) (void)hipFree(keys);
+      if (toff_dev) (void)hipFree(toff_dev);
+      if (err_dev) (void)hipFree(err_dev);
+    };
+    auto run = [&]() -> int {
+      CS_HIP(c, hipMalloc(&rec_in, sizeof(SampleRec) * N));
+      CS_HIP(c, hipMalloc(&keys, sizeof(unsigned long long) * np));
+      CS_HIP(c, hipMalloc(&toff_dev, sizeof(long long) * (c->ntiles + 1)));
+      CS_HIP(c, hipMalloc(&err_dev, sizeof(int)));
+      CS_HIP(c, hipMemsetAsync(err_dev, 0, sizeof(int), c->stream));
+      SetupGeom g{};
+      g.nd = nd;
+      for (int a = 0; a < 3; ++a) {
+        g.n[a] = n[a];
+        g.m[a] = m[a];
+        g.T[a] = c->tile[a];
+        g.nt[a] = c->ntile[a];
+      }
+      g.beta = c->beta;
+      hipLaunchKernelGGL(k_setup_samples, dim3(blocks_for(N, 256)), dim3(256), 0, c->stream,
+                         coords_dev, dcf_dev, N, g, rec_in, keys, err_dev);
+      if (np > N)
+        hipLaunchKernelGGL(k_fill_keys, dim3(blocks_for(np - N, 256)), dim3(256), 0, c->stream,
+                           keys, N, np);
+      const unsigned nb = (unsigned)(np / kSortBlock);
+      hipLaunchKernelGGL(k_bitonic_local, dim3(nb), dim3(1024), 0, c->stream, keys, 2LL,
+                         (long long)kSortBlock);
+      for (long long k = 2 * kSortBlock; k <= np; k *= 2) {
+        for (long long j = k / 2; j >= kSortBlock; j /= 2)
+          hipLaunchKernelGGL(k_bitonic_global, dim3(blocks_for(np / 2, 256)), dim3(256), 0,
+                             c->stream, keys, np, j, k);
+        hipLaunchKernelGGL(k_bitonic_local, dim3(nb), dim3(1024), 0, c->stream, keys, k, k);
+      }
+      CS_HIP(c, hipGetLastError());
+      hipLaunchKernelGGL(k_gather_sorted, dim3(blocks_for(N, 256)), dim3(256), 0, c->stream,
+                         keys, rec_in, N, c->rec);
+      hipLaunchKernelGGL(k_tile_offsets, dim3(blocks_for(c->ntiles + 1, 256)), dim3(256), 0,
+                         c->stream, keys, N, c->ntiles, tv, toff_dev);
+      CS_HIP(c, hipGetLastError());
+      int err = 0;
+      CS_HIP(c, hipMemcpyAsync(&err, err_dev, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      CS_HIP(c, hipMemcpyAsync(toff.data(), toff_dev, sizeof(long long) * (c->ntiles + 1),
+                               hipMemcpyDeviceToHost, c->stream));
+      CS_HIP(c, hipStreamSynchronize(c->stream));
+      if (err & 1) return fail(c, CS_EINVAL, "coordinate outside [-n/2, n/2)");
+      if (err & 2) return fail(c, CS_EINVAL, "density compensation must be >= 0");
+      return CS_OK;
+    };
+    const int rc = run();
+    release();
+    if (rc != CS_OK) return rc;
+  }
   if (dcf_dev) {
     CS_HIP(c, hipMalloc(&c->dcf_orig, sizeof(float) * N));
-    CS_HIP(c, hipMemcpy(c->dcf_orig, dcf.data(), sizeof(float) * N, hipMemcpyHostToDevice));
+    CS_HIP(c, hipMemcpyAsync(c->dcf_orig, dcf_dev, sizeof(float) * N, hipMemcpyDeviceToDevice,
+                             c->stream));
   }
 
   // work items: each tile's samples in chunks of at most `chunk`; the slot of

@@ -98,3 +98,34 @@ def test_reserved_recon_buffers_leave_the_result_unchanged():
             res.append(h(r.x))
             ctx.close()
         assert np.array_equal(res[0], res[1]), opts
+
+
+def test_operator_setup_rejects_bad_trajectories():
+    """The trajectory is checked on the GPU while it is binned: a coordinate
+    outside [-n/2, n/2) or a negative density weight fails cs_set_operator
+    with CS_EINVAL and its message, and a good trajectory set afterwards on
+    the same context works."""
+    dev()
+    from paper_2305_06482_amd import Context
+    from paper_2305_06482_amd.binding import CSError
+    case("set_operator on bad trajectories (16x24x24, C=3)")
+    shape = (16, 24, 24)
+    coords = synth.cones_traj(shape, 40, 16, seed=8).astype(np.float32)
+    dcf = synth.cones_dcf(coords, shape).astype(np.float32)
+    maps = synth.coil_maps(shape, 3, 9)
+    ctx = Context(shape, 3, "noncart", nsamp=coords.shape[0], wav_levels=2)
+    bad = coords.copy()
+    bad[17, 1] = 12.0  # y frequency n_y / 2: outside [-12, 12)
+    with pytest.raises(CSError, match="coordinate outside"):
+        ctx.set_operator(t(maps), coords=t(bad), dcf=t(dcf))
+    badw = dcf.copy()
+    badw[5] = -1.0
+    with pytest.raises(CSError, match="density compensation"):
+        ctx.set_operator(t(maps), coords=t(coords), dcf=t(badw))
+    with pytest.raises(CSError, match="cs_set_operator has not been called"):
+        ctx.normal_apply(t(maps), t(synth.phantom(shape, 2)))
+    ctx.set_operator(t(maps), coords=t(coords), dcf=t(dcf))
+    plan = nufft.Plan(shape, coords.astype(np.float64), dcf.astype(np.float64))
+    x = synth.phantom(shape, 2)
+    assert rel(h(ctx.normal_apply(t(maps), t(x))), plan.normal(x, maps)) < 1e-4
+    ctx.close()
