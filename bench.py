@@ -248,6 +248,7 @@ def time_to_accuracy(ctx, y, p, args, log, ref_iters, full_iters, outer_iters, c
     the context stream: `loop_ms` covers the iterations up to the first one
     within the threshold, `total_ms` adds the set-up (b = A^H y, step size by
     power iteration, PCA basis and first sketch)."""
+    import numpy as np
     import torch
     lam = p.lam if lam is None else lam
     C, V, S = p.n_coils, p.V, p.S
@@ -751,6 +752,39 @@ def batched_bench(args, log, T=3, K=5):
            "apply_model_bytes_per_outer_iteration": int(apply_bytes),
            "coil_samples_total": int(sum(p.coords.shape[0] * p.n_coils for p, *_ in sl)),
            "outer_iterations": T, "K": K, "spread_shapes": {str(k): v for k, v in tuned.items()}}
+    # the applies alone, as the batched path issues them: each slice's
+    # one full-coil and K sketched normal applies on its own stream, all
+    # slices at once; wall time between two events that bracket every stream
+    sk_maps = [ctx.sketch_build(y, p.V, p.S, p.seed, 1, host_outputs=False)[0]
+               for p, ctx, _, y in sl]
+    probes = [torch.randn(p.shape, dtype=torch.complex64, device="cuda") for p, *_ in sl]
+    outs = [torch.empty_like(v) for v in probes]
+    torch.cuda.synchronize()
+    main = torch.cuda.current_stream()
+    walls = []
+    for _ in range(4):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(main)
+        ends = []
+        for (p, ctx, maps, _), sm, v, o in zip(sl, sk_maps, probes, outs):
+            ctx.stream.wait_event(e0)
+            ctx.normal_apply(maps, v, out=o)
+            for _ in range(K):
+                ctx.normal_apply(sm, v, out=o)
+            ev = torch.cuda.Event()
+            ev.record(ctx.stream)
+            ends.append(ev)
+        for ev in ends:
+            main.wait_event(ev)
+        e1.record(main)
+        torch.cuda.synchronize()
+        walls.append(e0.elapsed_time(e1))
+    apply_ms = float(np.median(walls[1:]))
+    res["applies_ms_per_outer_iteration"] = apply_ms
+    res["applies_model_GBs"] = apply_bytes / (apply_ms * 1e-3) / 1e9
+    res["applies_pct_hbm_roofline"] = 100 * res["applies_model_GBs"] / HBM_PEAK_GBS
+    log(f"batched: the applies of one outer iteration of all slices take {apply_ms:.2f} ms, "
+        f"{res['applies_model_GBs']:.0f} GB/s of modelled bytes")
     xs = {}
     for use_graph in (False, True, False, True):
         x = [torch.zeros(p.shape, dtype=torch.complex64, device="cuda") for p, *_ in sl]
@@ -848,7 +882,7 @@ def headline(out):
     keys = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
             "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config",
             "pct_hbm_roofline", "normal_apply_ms", "min_GBs", "hbm_copy_GBs", "roofline",
-            "cpu_baseline", "precision", "time_to_1e-3", "detail_file")
+            "kernel_frac", "cpu_baseline", "precision", "time_to_1e-3", "detail_file")
     h = {k: out[k] for k in keys if k in out}
     s = json.dumps(h, separators=(",", ":"))
     if len(s) > HEADLINE_MAX_CHARS:
@@ -903,6 +937,8 @@ def main():
     ap.add_argument("--tta-chunk", type=int, default=100)
     ap.add_argument("--tta-full-iters", type=int, default=3000)
     ap.add_argument("--tta-outer-iters", type=int, default=200)
+    ap.add_argument("--no-cart-tta", action="store_true",
+                    help="skip the Cartesian time-to-accuracy runs")
     ap.add_argument("--tta-sketch-seeds", type=int, default=3,
                     help="sketch seeds per Algorithm 1 run of the cones time to accuracy")
     # the paper's weight for the cones l1-wavelet reconstruction; at the
@@ -1067,6 +1103,10 @@ def main():
         "device_memory": mem,
         "kernels": kern,
         "roofline": roof,
+        # every modelled kernel kind's algorithmic bytes per second over the
+        # HBM peak, so the kinds beside the dominant one are on record too
+        "kernel_frac": {k: round(v["GB/s"] / HBM_PEAK_GBS, 4) for k, v in kern.items()
+                        if "GB/s" in v},
         "detail_file": args.detail,
     }
     out["hbm_copy"] = hbm_copy_bandwidth()
@@ -1125,7 +1165,7 @@ def run_studies(out, args, ctx, y, p, Ch, log):
                                            args.tta_chunk, cnn=net, lam=args.tta_lam,
                                            x_ref=xr, sketch_seeds=args.tta_sketch_seeds)
             net.close()
-        if not args.small:
+        if not args.small and not args.no_cart_tta:
             for pc in (synth.make_cart_small(), synth.make_cart_clinical()):
                 tta[pc.name] = cartesian_tta(pc, args, log)
             if args.tta_cart_seeds > 1:

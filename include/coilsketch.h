@@ -344,14 +344,18 @@ int cs_batch_recon(cs_batch* b, const void* const* y, const cs_recon_params* p,
                    void* const* x, int use_graph, cs_batch_stats* st);
 
 /* ---- spreading work-group shapes and their autotuner --------------------- */
-#define CS_SPREAD_NCFG 8
+#define CS_SPREAD_NCFG 13
 /* Select spreading shape cfg in [0, CS_SPREAD_NCFG) for this context (all
- * shapes give bit-identical results; they differ only in speed).  Shape 0,
- * the default, keeps the sample values of the 3D normal operator in vector
- * registers and broadcasts them with v_readlane; shape 7 stages them in LDS
- * (as every shape does for 2D and for the adjoint's caller data); 1-6 vary
- * the waves and coils per work-group.  CS_SPREAD_CFG in the environment
- * sets the default of new operators. */
+ * shapes give bit-identical results; they differ only in speed).  Shape 0
+ * keeps the sample values of the 3D normal operator in vector registers and
+ * broadcasts them with v_readlane; shape 8 does the same and reads a run's
+ * LDS voxel when the run opens rather than when it is flushed; shapes 9-11
+ * also hold every lane's kernel weights for a whole batch of 64 samples in
+ * registers (4 waves x 1 coil, 2 x 2, 1 x 4 per group), and shape 12, the
+ * default, is 9 with the values broadcast by DPP row broadcasts instead;
+ * shape 7 stages the values in LDS (as every shape does for 2D and for the
+ * adjoint's caller data); 1-6 vary the waves and coils per work-group.
+ * CS_SPREAD_CFG in the environment sets the default of new operators. */
 int cs_set_spread_cfg(cs_ctx* ctx, int cfg);
 /* Time a normal apply with the given maps (device [D][ncoil]) under every
  * shape (reps applies each, HIP events on the context stream), select the
@@ -365,9 +369,11 @@ int cs_autotune_spread(cs_ctx* ctx, const void* maps, int ncoil, int reps, int* 
  * CS_INTERP_NCFG)): 0 gathers every tap of a sample from the grid in global
  * memory; 1 (the default), 2 and 3 copy each work item's halo'd grid tile
  * into LDS first and gather from there, for coil groups of at most 8 (1), 12
- * (2) or 4 (3) coils in 3D.  All sum the taps in the same order.  The
+ * (2) or 4 (3) coils in 3D; 4 is 1 with the tile's (re, im) pairs
+ * interleaved in LDS (one 8-byte read per tap and coil).  All sum the taps in
+ * the same order.  The
  * environment variable CS_INTERP_CFG sets the default of new operators. */
-#define CS_INTERP_NCFG 4
+#define CS_INTERP_NCFG 5
 int cs_set_interp_cfg(cs_ctx* ctx, int cfg);
 
 /* ---- building blocks exposed for testing and benchmarking ---------------- */

@@ -42,8 +42,8 @@ EXPORTED = [
     "cs_cnn_get_params", "cs_cnn_set_params", "cs_cnn_forward", "cs_cnn_loss_grad",
     "cs_cnn_train_step", "cs_cnn_collect",
 ]
-SPREAD_NCFG = 8
-INTERP_NCFG = 4
+SPREAD_NCFG = 13
+INTERP_NCFG = 5
 NKERNELS = 12
 KERNEL_KINDS = ["fft_pass", "interp", "spread", "gather", "wavelet", "soft", "vec", "reduce",
                 "covariance", "eigensolver", "coil_mix", "spread_merge"]

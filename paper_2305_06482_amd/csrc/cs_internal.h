@@ -56,6 +56,7 @@ struct PassArgs {
   const float2* maps; int maps_ldc, maps_c0;
   const float* da;       // [n] per-row scale along the pass axis
   const float* dp;       // [P] per-pixel scale of the other axes
+  int xcd;               // 1: each XCD takes a contiguous range of panels
 };
 
 // Sample record of the sorted non-Cartesian trajectory (64 bytes): first tap
@@ -106,6 +107,7 @@ struct cs_ctx {
   // FFT pass panels: pixels per panel of an image pass (all coils of each)
   // and columns per panel of a grid pass (CS_FFT_PIX / CS_FFT_COLS)
   int fft_pix = 1, fft_cols = 16;
+  int fft_xcd = 1;                // XCD-contiguous panel order in the FFT passes
 
   // operator
   const float2* maps = nullptr;   // borrowed [D][C]

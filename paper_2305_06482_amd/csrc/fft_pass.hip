@@ -317,6 +317,15 @@ __device__ __forceinline__ void fft_panel(float2* buf, const float2* tw, int tr,
     fft_stages<L, TC, 0, 1, 1>(buf, tw, tr, tc);
 }
 
+// Work-groups are dealt to the 8 XCDs in turn (group b to XCD b mod 8), and
+// each XCD has an L2 of its own.  This order gives XCD x a contiguous range
+// of the logical groups instead, so that panels next to each other in memory
+// (sharing cache lines) run on the same L2.  A bijection on [0, G).
+__device__ __forceinline__ long long xcd_contiguous(long long b, long long G) {
+  const long long q = G >> 3, r = G & 7, x = b & 7, i = b >> 3;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 template <int L, int TC>
 __global__ __launch_bounds__(256) void k_pass_t(PassArgs a) {
   constexpr int TR = pass_rows<TC>();
@@ -326,7 +335,7 @@ __global__ __launch_bounds__(256) void k_pass_t(PassArgs a) {
   float2* tw = smem + L * TC;     // [L]
   const int tid = threadIdx.x;
   const int tc = tid % TC, tr = tid / TC;
-  const long long blk = blockIdx.x;
+  const long long blk = a.xcd ? xcd_contiguous(blockIdx.x, gridDim.x) : (long long)blockIdx.x;
   const long long outer = blk / a.nblk;
   const long long col0 = (blk - outer * a.nblk) * a.Wt;
   const int ncol = (int)min((long long)a.Wt, a.inner - col0);
@@ -513,6 +522,7 @@ int launch_pass(cs_ctx* c, PassArgs& a, long long n_outer) {
       TC = pass_tc_for((int)w);
     }
     if (fits(TC)) {
+      a.xcd = c->fft_xcd;
       a.Wt = (int)w;
       const long long nblk = (a.inner + a.Wt - 1) / a.Wt;
       a.nblk = nblk;

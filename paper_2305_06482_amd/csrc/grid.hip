@@ -31,6 +31,8 @@
 #include <cmath>
 #include <cstdlib>
 #include <numeric>
+#include <type_traits>
+#include <utility>
 
 #include "cs_internal.h"
 
@@ -109,7 +111,7 @@ struct Halo {
 // the same values.  The sum is scaled by w (W_FULL), sqrt(w) (W_SQRT) or 1,
 // and written to row `voff + k - kbeg` of `out` (values of the item group)
 // or, with caller_order, to row orig[k] (the caller's sample order).
-template <int NDIM, int CG, int NT, bool TILE>
+template <int NDIM, int CG, int NT, bool TILE, bool IL = false>
 __global__ __launch_bounds__(NT) void k_interp_items(
     const float2* __restrict__ G, int mx, int my, int mz, int cb,
     const SampleRec* __restrict__ rec, const GridItem* __restrict__ items, int item0,
@@ -144,8 +146,13 @@ __global__ __launch_bounds__(NT) void k_interp_items(
       for (int q = 0; q < CG; ++q) {
         float2 v = make_float2(0.f, 0.f);
         if (q < cga) v = src[q];
-        lds[(size_t)q * 2 * H::PLANE + a] = v.x;
-        lds[(size_t)q * 2 * H::PLANE + H::PLANE + a] = v.y;
+        if constexpr (IL) {
+          // interleaved (re, im) per voxel: one 8-byte LDS read per tap
+          reinterpret_cast<float2*>(lds)[(size_t)q * H::PLANE + a] = v;
+        } else {
+          lds[(size_t)q * 2 * H::PLANE + a] = v.x;
+          lds[(size_t)q * 2 * H::PLANE + H::PLANE + a] = v.y;
+        }
       }
     }
     __syncthreads();
@@ -174,9 +181,15 @@ __global__ __launch_bounds__(NT) void k_interp_items(
             const float w = wyz * r.wx[dx];
 #pragma unroll
             for (int q = 0; q < CG; ++q) {
-              const float* pl = lds + (size_t)q * 2 * H::PLANE + row + dx;
-              acc[q].x += w * pl[0];
-              acc[q].y += w * pl[H::PLANE];
+              if constexpr (IL) {
+                const float2 g = reinterpret_cast<const float2*>(lds)[(size_t)q * H::PLANE + row + dx];
+                acc[q].x += w * g.x;
+                acc[q].y += w * g.y;
+              } else {
+                const float* pl = lds + (size_t)q * 2 * H::PLANE + row + dx;
+                acc[q].x += w * pl[0];
+                acc[q].y += w * pl[H::PLANE];
+              }
             }
           }
         } else {
@@ -220,7 +233,7 @@ size_t interp_tile_lds_bytes() {
 
 // 512 threads per group in 3D, where the LDS tile allows only one or two
 // groups per compute unit
-template <int NDIM, int CG, bool TILE>
+template <int NDIM, int CG, bool TILE, bool IL = false>
 int interp_launch(cs_ctx* c, const float2* grid, int cb, int item0, int nitems, int wmode,
                   float2* out, int ldc, int c0, int caller_order) {
   const size_t lds = TILE ? interp_tile_lds_bytes<NDIM, CG>() : 0;
@@ -228,7 +241,7 @@ int interp_launch(cs_ctx* c, const float2* grid, int cb, int item0, int nitems, 
   const int ng = (cb + CG - 1) / CG;
   if (nitems <= 0) return CS_OK;
   constexpr int NT = NDIM == 3 ? 512 : 256;
-  auto kern = k_interp_items<NDIM, CG, NT, TILE>;
+  auto kern = k_interp_items<NDIM, CG, NT, TILE, IL>;
   if (lds > 64 * 1024)
     CS_HIP(c, hipFuncSetAttribute((const void*)kern,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -246,12 +259,15 @@ template <int NDIM>
 int interp_dispatch(cs_ctx* c, const float2* grid, int cb, int item0, int nitems, int wmode,
                     float2* out, int ldc, int c0, int caller_order) {
   const bool tile = c->interp_cfg >= 1;
+  const bool il = c->interp_cfg == 4;  // interleaved (re, im) LDS tile
   int cmax = c->interp_cfg == 2 ? 12 : (c->interp_cfg == 3 ? 4 : 8);
   if (NDIM == 2) cmax = 16;
   const int ng = (cb + cmax - 1) / cmax;
   const int cg = (cb + ng - 1) / ng;
 #define CS_ITILE(CG)                                                                        \
-  return tile ? interp_launch<NDIM, CG, true>(c, grid, cb, item0, nitems, wmode, out, ldc, \
+  return il ? interp_launch<NDIM, CG, true, true>(c, grid, cb, item0, nitems, wmode, out,  \
+                                                  ldc, c0, caller_order)                   \
+       : tile ? interp_launch<NDIM, CG, true>(c, grid, cb, item0, nitems, wmode, out, ldc, \
                                               c0, caller_order)                            \
               : interp_launch<NDIM, CG, false>(c, grid, cb, item0, nitems, wmode, out,     \
                                                ldc, c0, caller_order)
@@ -266,6 +282,9 @@ int interp_dispatch(cs_ctx* c, const float2* grid, int cb, int item0, int nitems
 }
 
 constexpr int kSpreadBatch = 64;  // samples staged in LDS per step
+// default spreading shape: register-held values and kernel weights, values
+// broadcast by DPP, 4 waves of one coil each (shape 12 of spread_dispatch)
+constexpr int kSpreadDefault = 12;
 // staged record: packed first tap, wx[4], then wy[dy] * wz[dz] at 4 dz + dy
 // (the products are formed once per sample in the staging, not by every
 // coil wave for every tap)
@@ -318,6 +337,7 @@ __global__ __launch_bounds__(64 * NW) void k_spread_items(
 
   const int tap = lane % H::NTAPS, cslot = lane / H::NTAPS;
   const int dx = tap & 3, dy = (tap >> 2) & 3, dz = tap >> 4;
+  const int loff = dz * H::PZ + dy * H::PY + dx;  // this lane's tap in the tile
   const int q0 = (wave * H::LPC + cslot) * CW;  // first group coil of this lane
   // waves whose coils all lie beyond the chunk only help with the staging
   const bool active = (wave * H::LPC) * CW < cga;
@@ -411,9 +431,11 @@ __global__ __launch_bounds__(64 * NW) void k_spread_items(
           }
         }
         rkey = __builtin_amdgcn_readfirstlane(__float_as_int(srec[s * SRP]));
-        const int lx = (rkey & 0xff) + dx, ly = ((rkey >> 8) & 0xff) + dy,
-                  lz = NDIM == 3 ? (rkey >> 16) + dz : 0;
-        raddr = lz * H::PZ + ly * H::PY + lx;
+        // the run's first tap is uniform: its offset is scalar arithmetic,
+        // and one vector add places this lane's tap
+        const int lz = NDIM == 3 ? (rkey >> 16) : 0;
+        raddr = __builtin_amdgcn_readfirstlane(lz * H::PZ + ((rkey >> 8) & 0xff) * H::PY +
+                                               (rkey & 0xff)) + loff;
       }
       // samples of the run: register accumulation, no branches
 #pragma unroll 4
@@ -452,14 +474,47 @@ __global__ __launch_bounds__(64 * NW) void k_spread_items(
   }
 }
 
+// f(std::integral_constant<int, i>) for i = 0 .. N-1, expanded at compile time
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// acc += src[lane j of this lane's row of 16] * w: a VOP2 FMA whose first
+// operand is read through the row broadcast of DPP (row_newbcast, CDNA3 and
+// later), so a value is broadcast and used in one instruction
+template <int J>
+__device__ __forceinline__ void fmac_rowbcast(float& acc, float src, float w) {
+  asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+               : "+v"(acc)
+               : "v"(src), "v"(w), "n"(J));
+}
+
 // The 3D spreading of the normal operator with the sample values held in
 // vector registers instead of LDS: lane j of a wave keeps sample j's values
 // of the wave's CW coils, and each sample's values are broadcast to the
 // wave's lanes by v_readlane into scalar registers that enter the FMAs as
 // scalar operands.  Only the kernel weights go through LDS.  Summation
 // order as in k_spread_items (bit-identical results).
-template <int NW, int CW>
-__global__ __launch_bounds__(64 * NW) void k_spread_rl(
+// VAR 0: a loop over the batch's runs, the weights read from LDS per sample;
+// VAR 1: the same, and the LDS value of a run's voxel is read when the run
+// opens, so that its flush only adds and writes;
+// VAR 2: every lane first forms its tap's weight for all samples of the
+// batch in registers, then one pass over the batch, unrolled so that the
+// weights are static register operands, takes the run starts from a bit
+// mask; no LDS access in the sample loop outside the run flushes, which
+// work as in VAR 1;
+// VAR 3: VAR 2 with the values broadcast by DPP instead of v_readlane: every
+// row of 16 lanes holds the values of the same 16 samples, and the FMA
+// reads sample j's through row_newbcast:j (one instruction per product).
+// (LDS admits at most three waves per SIMD; the register budget is held to
+// that occupancy.)
+template <int NW, int CW, int VAR>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) void k_spread_rl(
     const float2* __restrict__ V, int /*ldc*/, int /*c0*/, int cb,
     const SampleRec* __restrict__ rec,
     const GridItem* __restrict__ items, int item0, int ntx, int nty,
@@ -473,6 +528,8 @@ __global__ __launch_bounds__(64 * NW) void k_spread_rl(
   float* srec = acc + (size_t)CG * 2 * H::PLANE;  // [SB][SRP]
   __shared__ int s_rs[SB];
   __shared__ int s_nr;
+  __shared__ unsigned s_sm[2];  // run starts of the batch as a bit mask
+  constexpr bool PF = VAR >= 1;  // run's voxel read when it opens
 
   const GridItem it = items[item0 + blockIdx.x];
   const int tile = it.tile, kbeg = it.kbeg, kend = it.kend, slot = it.slot;
@@ -483,11 +540,15 @@ __global__ __launch_bounds__(64 * NW) void k_spread_rl(
   for (int i = tid; i < CG * 2 * H::PLANE; i += NT) acc[i] = 0.f;
 
   const int dx = lane & 3, dy = (lane >> 2) & 3, dz = lane >> 4;
+  const int loff = dz * H::PZ + dy * H::PY + dx;  // this lane's tap in the tile
   const int q0 = wave * CW;  // first group coil of this wave
   const bool active = q0 < cga;
   float2 racc[CW];
+  // PF: the LDS value of the run's voxel, read when the run opens (the lane
+  // owns the voxel until it flushes), so the flush only adds and writes
+  float2 rbase[CW];
 #pragma unroll
-  for (int q = 0; q < CW; ++q) racc[q] = make_float2(0.f, 0.f);
+  for (int q = 0; q < CW; ++q) racc[q] = rbase[q] = make_float2(0.f, 0.f);
   int rkey = -1, raddr = 0;
 
   // thread t < SB fetches the record of sample t of the next batch; lane j of
@@ -537,13 +598,93 @@ __global__ __launch_bounds__(64 * NW) void k_spread_rl(
       const bool start = tid < n && pkey != (tid > 0 ? prev : rkey);
       const unsigned long long mask = __ballot(start);
       if (start) s_rs[__popcll(mask & ((1ull << tid) - 1ull))] = tid;
-      if (tid == 0) s_nr = __popcll(mask);
+      if (tid == 0) {
+        s_nr = __popcll(mask);
+        s_sm[0] = (unsigned)mask;
+        s_sm[1] = (unsigned)(mask >> 32);
+      }
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < CW; ++q)
       cv[q] = make_float2(sval[((wave * CW + q) * 2) * 64 + lane],
                           sval[((wave * CW + q) * 2 + 1) * 64 + lane]);
+    if constexpr (VAR >= 2) {
+      static_assert(SB == 64, "one run-start bit and one value lane per sample");
+      // VAR 3: chunk c of 16 samples, sample 16 c + (lane & 15) in every row
+      float2 cr[CW][4];
+      if constexpr (VAR == 3) {
+#pragma unroll
+        for (int q = 0; q < CW; ++q)
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            cr[q][c] = make_float2(sval[((wave * CW + q) * 2) * 64 + 16 * c + (lane & 15)],
+                                   sval[((wave * CW + q) * 2 + 1) * 64 + 16 * c + (lane & 15)]);
+      }
+      const int vkey = __float_as_int(srec[lane * SRP]);
+      const unsigned sm0 = __builtin_amdgcn_readfirstlane(s_sm[0]),
+                     sm1 = __builtin_amdgcn_readfirstlane(s_sm[1]);
+      if (k0 + SB < kend) prefetch(k0 + SB, min(SB, kend - k0 - SB));
+      // rows s >= n hold stale records: their weights are formed, never
+      // used.  All reads are issued before the first product; the empty asm
+      // statements keep the products ahead of the sample loop (rather than
+      // inside its run branches)
+      float wr[SB];
+#pragma unroll
+      for (int s = 0; s < SB; ++s) {
+        const float* d = srec + s * SRP;
+        wr[s] = d[1 + dx] * d[5 + dy + 4 * dz];
+      }
+#pragma unroll
+      for (int s = 0; s < SB; ++s) asm volatile("" : "+v"(wr[s]));
+      if (active) {
+        // one step per sample, expanded at compile time (the broadcast lane
+        // and the weight register are constants of each step)
+        auto step = [&](auto sc) {
+          constexpr int s = decltype(sc)::value;
+          if (s >= n) return;
+          if (((s < 32 ? sm0 : sm1) >> (s & 31)) & 1u) {
+            // the LDS value of the run's voxel was read when the run opened
+            // (a run's voxels are this lane's alone until it flushes), so
+            // the flush rarely waits
+            if (rkey >= 0) {
+#pragma unroll
+              for (int q = 0; q < CW; ++q) {
+                float* pl = acc + (size_t)(q0 + q) * 2 * H::PLANE + raddr;
+                pl[0] = rbase[q].x + racc[q].x;
+                pl[H::PLANE] = rbase[q].y + racc[q].y;
+                racc[q] = make_float2(0.f, 0.f);
+              }
+            }
+            rkey = __builtin_amdgcn_readlane(vkey, s);
+            raddr = __builtin_amdgcn_readfirstlane((rkey >> 16) * H::PZ +
+                                                   ((rkey >> 8) & 0xff) * H::PY +
+                                                   (rkey & 0xff)) + loff;
+#pragma unroll
+            for (int q = 0; q < CW; ++q) {
+              const float* pl = acc + (size_t)(q0 + q) * 2 * H::PLANE + raddr;
+              rbase[q] = make_float2(pl[0], pl[H::PLANE]);
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < CW; ++q) {
+            if constexpr (VAR == 3) {
+              fmac_rowbcast<(s & 15)>(racc[q].x, cr[q][s >> 4].x, wr[s]);
+              fmac_rowbcast<(s & 15)>(racc[q].y, cr[q][s >> 4].y, wr[s]);
+            } else {
+              const float vr =
+                  __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cv[q].x), s));
+              const float vi =
+                  __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cv[q].y), s));
+              racc[q].x += wr[s] * vr;
+              racc[q].y += wr[s] * vi;
+            }
+          }
+        };
+        static_for<SB>(step);
+      }
+      continue;
+    }
     // lane j: key of sample j and start of run j of the batch (broadcast
     // by v_readlane below instead of a LDS round trip per run)
     const int vkey = __float_as_int(srec[lane * SRP]);
@@ -571,18 +712,41 @@ __global__ __launch_bounds__(64 * NW) void k_spread_rl(
 #pragma unroll
           for (int q = 0; q < CW; ++q) {
             float* pl = acc + (size_t)(q0 + q) * 2 * H::PLANE + raddr;
-            pl[0] += racc[q].x;
-            pl[H::PLANE] += racc[q].y;
+            if constexpr (PF) {
+              pl[0] = rbase[q].x + racc[q].x;
+              pl[H::PLANE] = rbase[q].y + racc[q].y;
+            } else {
+              pl[0] += racc[q].x;
+              pl[H::PLANE] += racc[q].y;
+            }
             racc[q] = make_float2(0.f, 0.f);
           }
         }
         rkey = __builtin_amdgcn_readlane(vkey, s);
-        const int lx = (rkey & 0xff) + dx, ly = ((rkey >> 8) & 0xff) + dy,
-                  lz = (rkey >> 16) + dz;
-        raddr = lz * H::PZ + ly * H::PY + lx;
+        raddr = __builtin_amdgcn_readfirstlane((rkey >> 16) * H::PZ + ((rkey >> 8) & 0xff) * H::PY +
+                                               (rkey & 0xff)) + loff;
+        if constexpr (PF) {
+#pragma unroll
+          for (int q = 0; q < CW; ++q) {
+            const float* pl = acc + (size_t)(q0 + q) * 2 * H::PLANE + raddr;
+            rbase[q] = make_float2(pl[0], pl[H::PLANE]);
+          }
+        }
       }
       // unrolled by hand (the broadcasts are convergent operations, which
       // the compiler does not unroll at a run-time trip count)
+      if constexpr (PF) {
+        for (; s + 8 <= s1; s += 8) {
+          one(s);
+          one(s + 1);
+          one(s + 2);
+          one(s + 3);
+          one(s + 4);
+          one(s + 5);
+          one(s + 6);
+          one(s + 7);
+        }
+      }
       for (; s + 4 <= s1; s += 4) {
         one(s);
         one(s + 1);
@@ -596,8 +760,13 @@ __global__ __launch_bounds__(64 * NW) void k_spread_rl(
 #pragma unroll
     for (int q = 0; q < CW; ++q) {
       float* pl = acc + (size_t)(q0 + q) * 2 * H::PLANE + raddr;
-      pl[0] += racc[q].x;
-      pl[H::PLANE] += racc[q].y;
+      if constexpr (PF) {
+        pl[0] = rbase[q].x + racc[q].x;
+        pl[H::PLANE] = rbase[q].y + racc[q].y;
+      } else {
+        pl[0] += racc[q].x;
+        pl[H::PLANE] += racc[q].y;
+      }
     }
   }
   __syncthreads();
@@ -704,7 +873,7 @@ size_t spread_lds_bytes() {
   return sizeof(float) * ((size_t)CG * 2 * H::PLANE + SR + (size_t)4 * kSpreadBatch * CG);
 }
 
-template <int NDIM, int NW, int CW, bool SV = false>
+template <int NDIM, int NW, int CW, bool SV = false, int VAR = 0>
 int spread_items_launch(cs_ctx* c, int src, const float2* vals, int ldc, int c0, int cb,
                         int item0, int nitems) {
   using H = Halo<NDIM>;
@@ -720,7 +889,7 @@ int spread_items_launch(cs_ctx* c, int src, const float2* vals, int ldc, int c0,
                         : spread_lds_bytes<NDIM, NW, CW>();
   if (lds > 160 * 1024) return fail(c, CS_EINVAL, "spread tile does not fit in LDS");
   if (nitems <= 0) return CS_OK;
-  auto kern = rl ? k_spread_rl<NW, CW>
+  auto kern = rl ? k_spread_rl<NW, CW, VAR>
                  : (src == SRC_VALS ? k_spread_items<NDIM, NW, CW, SRC_VALS>
                                     : k_spread_items<NDIM, NW, CW, SRC_DATA>);
   if (lds > 64 * 1024)
@@ -758,13 +927,18 @@ int spread_dispatch(cs_ctx* c, int what, int src, const float2* vals, int ldc, i
   return what == 0 ? spread_items_launch<NDIM, NW, CW>(c, src, vals, ldc, c0, cb, item0,  \
                                                        nitems)                             \
                    : merge_launch<NDIM, NW, CW>(c, cb, grid)
-#define CS_SHAPE_SV(NW, CW)                                                                \
-  return what == 0 ? spread_items_launch<NDIM, NW, CW, true>(c, src, vals, ldc, c0, cb,   \
-                                                             item0, nitems)                \
+#define CS_SHAPE_SV(NW, CW, VAR)                                                           \
+  return what == 0 ? spread_items_launch<NDIM, NW, CW, true, VAR>(c, src, vals, ldc, c0,  \
+                                                                 cb, item0, nitems)        \
                    : merge_launch<NDIM, NW, CW>(c, cb, grid)
   switch (c->spread_cfg) {
-    case 0: CS_SHAPE_SV(4, 1);
+    case 0: CS_SHAPE_SV(4, 1, 0);
     case 7: CS_SHAPE(4, 1);
+    case 8: CS_SHAPE_SV(4, 1, 1);
+    case 9: CS_SHAPE_SV(4, 1, 2);
+    case 10: CS_SHAPE_SV(2, 2, 2);
+    case 11: CS_SHAPE_SV(1, 4, 2);
+    case 12: CS_SHAPE_SV(4, 1, 3);
     case 1: CS_SHAPE(2, 2);
     case 2: CS_SHAPE(2, 1);
     case 3: CS_SHAPE(1, 4);
@@ -782,7 +956,7 @@ int spread_dispatch(cs_ctx* c, int what, int src, const float2* vals, int ldc, i
       } else {
         CS_SHAPE(4, 1);
       }
-    default: CS_SHAPE_SV(4, 1);
+    default: CS_SHAPE_SV(4, 1, 0);
   }
 #undef CS_SHAPE
 #undef CS_SHAPE_SV
@@ -989,7 +1163,7 @@ int setup_noncart(cs_ctx* c, const float* coords_dev, const float* dcf_dev) {
   for (int a = 3 - nd; a < 3; ++a)
     if (m[a] < 4) return fail(c, CS_EINVAL, "NUFFT grid shorter than the kernel");
   const char* cfg = std::getenv("CS_SPREAD_CFG");
-  c->spread_cfg = cfg ? std::atoi(cfg) : 0;
+  c->spread_cfg = cfg ? std::atoi(cfg) : kSpreadDefault;
   const char* icfg = std::getenv("CS_INTERP_CFG");
   c->interp_cfg = icfg ? std::atoi(icfg) : 1;
   // samples per item group of the normal operator (CS_GROUP_SAMPLES in the

@@ -79,6 +79,7 @@ def _stub_record():
         "roofline": {"bound": "hbm", "kernel": "spread", "achieved": 500.0, "peak": 8000.0,
                      "unit": "GB/s", "frac": 0.0625, "traffic": None, "avg_launch_ms": 2.0,
                      "bytes_per_launch": 1.0e9},
+        "kernel_frac": {"fft_pass": 0.38, "interp": 0.13, "spread": 0.1},
         "cpu_baseline": {"value": 0.4, "unit": "GB/s", "cores": 12, "kind": "oracle",
                          "sample": "x" * 200, "seconds_per_apply": 25.0},
         "precision": {"normal_apply_one_coil_rel_l2": 4e-7, "coil_mix_split_bf16_rel_l2": 1e-7},
@@ -105,6 +106,7 @@ def test_headline_line_is_compact_and_complete():
     for k in ("value", "unit", "cores", "kind", "sample"):
         assert k in h["cpu_baseline"], k
     assert "kernels" not in h and "time_to_accuracy" not in h
+    assert h["kernel_frac"]["spread"] == 0.1
     assert h["config"]["workload"].startswith("cones3d")
 
 

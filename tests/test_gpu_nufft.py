@@ -98,7 +98,8 @@ def test_normal_is_deterministic():
                                     ("cones", 12), ("cones", 32)])
 def test_interp_variants_agree(kind, C):
     """The global-memory gather (variant 0) and the LDS-tile interpolation
-    (variants 1, 2, 3: coil groups of 8, 12, 4) against the oracle and
+    (variants 1, 2, 3: coil groups of 8, 12, 4; 4: variant 1 with the tile
+    interleaved as (re, im) pairs) against the oracle and
     against each other: same taps, same summation order.  Shapes with partial edge tiles (grid 30 = 3 x 8 + 6),
     odd coil counts (guarded group lanes), a grid shorter than the tile and
     two coil chunks."""
@@ -120,10 +121,10 @@ def test_interp_variants_agree(kind, C):
     x = synth.phantom(shape, 2) + 0.1 * rng_c(shape, 11)
     mt, xt = t(maps), t(x)
     out = {}
-    for v in (0, 1, 2, 3):
+    for v in (0, 1, 2, 3, 4):
         ctx.set_interp_cfg(v)
         out[v] = (h(ctx.sense_apply(mt, xt)), h(ctx.normal_apply(mt, xt)))
-    for v in (1, 2, 3):
+    for v in (1, 2, 3, 4):
         assert rel(out[v][0], plan.forward(x, maps)) < TOL
         assert rel(out[v][1], plan.normal(x, maps)) < TOL
         for a, b in zip(out[0], out[v]):
