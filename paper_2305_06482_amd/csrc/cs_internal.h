@@ -108,6 +108,7 @@ struct cs_ctx {
   // and columns per panel of a grid pass (CS_FFT_PIX / CS_FFT_COLS)
   int fft_pix = 1, fft_cols = 16;
   int fft_xcd = 1;                // XCD-contiguous panel order in the FFT passes
+  int grid_xcd = 1;               // gridding: an item's coil groups on one XCD
 
   // operator
   const float2* maps = nullptr;   // borrowed [D][C]

@@ -103,6 +103,31 @@ struct Halo {
   static constexpr int LPC = 64 / NTAPS;  // coil slots per wave
 };
 
+// Work item (relative to item0) and coil group of this work-group.  With a
+// two-dimensional grid (items, groups) they are blockIdx.x and blockIdx.y.
+// With xcd the grid is one-dimensional and the coil groups of item i sit at
+// blocks 8 (ng (i / 8) + g) + i % 8: work-groups are dealt to the 8 XCDs in
+// turn, so all groups of an item run on one XCD, close together in time,
+// and every group after the first finds the item's sample records (and, for
+// the interpolation, its grid tile) in that XCD's L2.  False for the padding
+// blocks past the last item.
+__device__ __forceinline__ bool item_and_group(int nitems, int ng, int xcd, int& item,
+                                               int& g) {
+  if (!xcd) {
+    item = blockIdx.x;
+    g = blockIdx.y;
+    return true;
+  }
+  const int b = blockIdx.x, t = b >> 3;
+  g = t % ng;
+  item = (t / ng) * 8 + (b & 7);
+  return item < nitems;
+}
+
+inline dim3 item_group_grid(long long nitems, int ng, int xcd) {
+  return xcd ? dim3((unsigned)(((nitems + 7) / 8) * 8 * ng)) : dim3((unsigned)nitems, (unsigned)ng);
+}
+
 // Interpolation: one work-group per work item and coil group.  With TILE the
 // group first copies the item's halo'd tile of the grid into LDS, planar per
 // (coil, re/im) as in the spreading accumulator; without it the taps are
@@ -116,12 +141,14 @@ __global__ __launch_bounds__(NT) void k_interp_items(
     const float2* __restrict__ G, int mx, int my, int mz, int cb,
     const SampleRec* __restrict__ rec, const GridItem* __restrict__ items, int item0,
     int ntx, int nty, int wmode, float2* __restrict__ out, int ldc, int c0,
-    int caller_order) {
+    int caller_order, int nitems, int xcd) {
   using H = Halo<NDIM>;
   extern __shared__ float lds[];  // [CG][2][PLANE]
-  const GridItem it = items[item0 + blockIdx.x];
+  int item, grp;
+  if (!item_and_group(nitems, (cb + CG - 1) / CG, xcd, item, grp)) return;
+  const GridItem it = items[item0 + item];
   const int tile = it.tile, kbeg = it.kbeg, kend = it.kend;
-  const int cg0 = blockIdx.y * CG, cga = min(CG, cb - cg0);
+  const int cg0 = grp * CG, cga = min(CG, cb - cg0);
   const int ix = tile % ntx, iy = (tile / ntx) % nty, iz = tile / (ntx * nty);
   const int x0 = ix * H::TX, y0 = iy * H::TY, z0 = iz * H::TZ;
   const int tid = threadIdx.x;
@@ -245,9 +272,9 @@ int interp_launch(cs_ctx* c, const float2* grid, int cb, int item0, int nitems, 
   if (lds > 64 * 1024)
     CS_HIP(c, hipFuncSetAttribute((const void*)kern,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  CS_KLAUNCH(c, K_INTERP, kern, dim3((unsigned)nitems, (unsigned)ng), dim3(NT), lds, c->stream,
-             grid, c->mx, c->my, c->mz, cb, c->rec, c->gitems, item0, c->ntile[2],
-             c->ntile[1], wmode, out, ldc, c0, caller_order);
+  CS_KLAUNCH(c, K_INTERP, kern, item_group_grid(nitems, ng, c->grid_xcd), dim3(NT), lds,
+             c->stream, grid, c->mx, c->my, c->mz, cb, c->rec, c->gitems, item0, c->ntile[2],
+             c->ntile[1], wmode, out, ldc, c0, caller_order, nitems, c->grid_xcd);
   CS_HIP(c, hipGetLastError());
   return CS_OK;
 }
@@ -308,7 +335,7 @@ template <int NDIM, int NW, int CW, int SRC>
 __global__ __launch_bounds__(64 * NW) void k_spread_items(
     const float2* __restrict__ V, int ldc, int c0, int cb, const SampleRec* __restrict__ rec,
     const GridItem* __restrict__ items, int item0, int ntx, int nty,
-    float2* __restrict__ P) {
+    float2* __restrict__ P, int nitems, int xcd) {
   using H = Halo<NDIM>;
   constexpr int NT = 64 * NW;
   constexpr int CG = NW * H::LPC * CW;
@@ -325,9 +352,11 @@ __global__ __launch_bounds__(64 * NW) void k_spread_items(
   __shared__ int s_rs[SB];  // run starts of the staged batch
   __shared__ int s_nr;
 
-  const GridItem it = items[item0 + blockIdx.x];
+  const int ng = (cb + CG - 1) / CG;
+  int item, g;
+  if (!item_and_group(nitems, ng, xcd, item, g)) return;
+  const GridItem it = items[item0 + item];
   const int tile = it.tile, kbeg = it.kbeg, kend = it.kend, slot = it.slot;
-  const int g = blockIdx.y, ng = gridDim.y;
   const int cg0 = g * CG, cga = min(CG, cb - cg0);
   // the wave index through readfirstlane: the compiler then knows it (and
   // all that depends only on it) to be uniform across the wave
@@ -518,7 +547,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
     const float2* __restrict__ V, int /*ldc*/, int /*c0*/, int cb,
     const SampleRec* __restrict__ rec,
     const GridItem* __restrict__ items, int item0, int ntx, int nty,
-    float2* __restrict__ P) {
+    float2* __restrict__ P, int nitems, int xcd) {
   using H = Halo<3>;
   constexpr int NT = 64 * NW;
   constexpr int CG = NW * CW;
@@ -531,9 +560,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
   __shared__ unsigned s_sm[2];  // run starts of the batch as a bit mask
   constexpr bool PF = VAR >= 1;  // run's voxel read when it opens
 
-  const GridItem it = items[item0 + blockIdx.x];
+  const int ng = (cb + CG - 1) / CG;
+  int item, g;
+  if (!item_and_group(nitems, ng, xcd, item, g)) return;
+  const GridItem it = items[item0 + item];
   const int tile = it.tile, kbeg = it.kbeg, kend = it.kend, slot = it.slot;
-  const int g = blockIdx.y, ng = gridDim.y;
   const int cg0 = g * CG, cga = min(CG, cb - cg0);
   const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6),
             lane = tid & 63;
@@ -895,9 +926,9 @@ int spread_items_launch(cs_ctx* c, int src, const float2* vals, int ldc, int c0,
   if (lds > 64 * 1024)
     CS_HIP(c, hipFuncSetAttribute((const void*)kern,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  CS_KLAUNCH(c, K_SPREAD, kern, dim3((unsigned)nitems, (unsigned)ng), dim3(64 * NW), lds,
+  CS_KLAUNCH(c, K_SPREAD, kern, item_group_grid(nitems, ng, c->grid_xcd), dim3(64 * NW), lds,
              c->stream, vals, ldc, c0, cb, c->rec, c->gitems, item0, c->ntile[2],
-             c->ntile[1], c->partial);
+             c->ntile[1], c->partial, nitems, c->grid_xcd);
   CS_HIP(c, hipGetLastError());
   return CS_OK;
 }
@@ -1164,6 +1195,7 @@ int setup_noncart(cs_ctx* c, const float* coords_dev, const float* dcf_dev) {
     if (m[a] < 4) return fail(c, CS_EINVAL, "NUFFT grid shorter than the kernel");
   const char* cfg = std::getenv("CS_SPREAD_CFG");
   c->spread_cfg = cfg ? std::atoi(cfg) : kSpreadDefault;
+  if (const char* e = std::getenv("CS_GRID_XCD")) c->grid_xcd = std::atoi(e) != 0;
   const char* icfg = std::getenv("CS_INTERP_CFG");
   c->interp_cfg = icfg ? std::atoi(icfg) : 1;
   // samples per item group of the normal operator (CS_GROUP_SAMPLES in the
