@@ -352,7 +352,9 @@ int cs_batch_recon(cs_batch* b, const void* const* y, const cs_recon_params* p,
  * LDS voxel when the run opens rather than when it is flushed; shapes 9-11
  * also hold every lane's kernel weights for a whole batch of 64 samples in
  * registers (4 waves x 1 coil, 2 x 2, 1 x 4 per group), and shape 12, the
- * default, is 9 with the values broadcast by DPP row broadcasts instead;
+ * default, is 9 with the values broadcast by DPP row broadcasts instead (in
+ * 2D and for the adjoint's caller data, shapes 9-12 run the same
+ * register-weight loop with DPP broadcasts on LDS-staged values);
  * shape 7 stages the values in LDS (as every shape does for 2D and for the
  * adjoint's caller data); 1-6 vary the waves and coils per work-group.
  * CS_SPREAD_CFG in the environment sets the default of new operators. */

@@ -318,6 +318,103 @@ constexpr int kSpreadDefault = 12;
 constexpr int kSpreadRecPitch = 21;
 enum { SRC_VALS = 0, SRC_DATA = 1 };
 
+// f(std::integral_constant<int, i>) for i = 0 .. N-1, expanded at compile time
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// acc += src[lane j of this lane's row of 16] * w: a VOP2 FMA whose first
+// operand is read through the row broadcast of DPP (row_newbcast, CDNA3 and
+// later), so a value is broadcast and used in one instruction
+template <int J>
+__device__ __forceinline__ void fmac_rowbcast(float& acc, float src, float w) {
+  asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+               : "+v"(acc)
+               : "v"(src), "v"(w), "n"(J));
+}
+
+// One batch of the register-weight spreading (k_spread_rl VAR 2 and 3,
+// k_spread_items with RW): every lane forms its tap's weight for all
+// samples of the batch in registers, then one pass over the batch, expanded
+// at compile time (the weight register and, with DPP, the broadcast lane
+// are constants of each step), takes the run starts from the bit mask
+// sm1:sm0 and keeps the run state (racc, rbase, rkey, raddr) across batches.
+// Values: with DPP chunk c of 16 samples in cr[q][c] (sample 16 c + j in
+// lane j of every row of 16), else sample j's in lane j of cv[q].  Lanes
+// beyond the staged rows form weights from stale records, never used.
+template <int NDIM, int CW, bool DPP>
+__device__ __forceinline__ void rw_batch(float* acc, const float* srec, int n, unsigned sm0,
+                                         unsigned sm1, int vkey, int q0, int loff, int dx,
+                                         int dy, int dz, bool active,
+                                         const float2 (&cr)[CW][4], const float2 (&cv)[CW],
+                                         float2 (&racc)[CW], float2 (&rbase)[CW], int& rkey,
+                                         int& raddr) {
+  using H = Halo<NDIM>;
+  constexpr int SB = kSpreadBatch, SRP = kSpreadRecPitch;
+  // rows s >= n hold stale records: their weights are formed, never
+  // used.  All reads are issued before the first product; the empty asm
+  // statements keep the products ahead of the sample loop (rather than
+  // inside its run branches)
+  float wr[SB];
+#pragma unroll
+  for (int s = 0; s < SB; ++s) {
+    const float* d = srec + s * SRP;
+    wr[s] = d[1 + dx] * d[5 + dy + 4 * dz];
+  }
+#pragma unroll
+  for (int s = 0; s < SB; ++s) asm volatile("" : "+v"(wr[s]));
+  if (!active) return;
+  // one step per sample, expanded at compile time (the broadcast lane
+  // and the weight register are constants of each step)
+  auto step = [&](auto sc) {
+    constexpr int s = decltype(sc)::value;
+    if (s >= n) return;
+    if (((s < 32 ? sm0 : sm1) >> (s & 31)) & 1u) {
+      // the LDS value of the run's voxel was read when the run opened
+      // (a run's voxels are this lane's alone until it flushes), so
+      // the flush rarely waits
+      if (rkey >= 0) {
+#pragma unroll
+        for (int q = 0; q < CW; ++q) {
+          float* pl = acc + (size_t)(q0 + q) * 2 * H::PLANE + raddr;
+          pl[0] = rbase[q].x + racc[q].x;
+          pl[H::PLANE] = rbase[q].y + racc[q].y;
+          racc[q] = make_float2(0.f, 0.f);
+        }
+      }
+      rkey = __builtin_amdgcn_readlane(vkey, s);
+      raddr = __builtin_amdgcn_readfirstlane((rkey >> 16) * H::PZ +
+                                             ((rkey >> 8) & 0xff) * H::PY +
+                                             (rkey & 0xff)) + loff;
+#pragma unroll
+      for (int q = 0; q < CW; ++q) {
+        const float* pl = acc + (size_t)(q0 + q) * 2 * H::PLANE + raddr;
+        rbase[q] = make_float2(pl[0], pl[H::PLANE]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+      if constexpr (DPP) {
+        fmac_rowbcast<(s & 15)>(racc[q].x, cr[q][s >> 4].x, wr[s]);
+        fmac_rowbcast<(s & 15)>(racc[q].y, cr[q][s >> 4].y, wr[s]);
+      } else {
+        const float vr =
+            __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cv[q].x), s));
+        const float vi =
+            __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cv[q].y), s));
+        racc[q].x += wr[s] * vr;
+        racc[q].y += wr[s] * vi;
+      }
+    }
+  };
+  static_for<SB>(step);
+}
+
 // One work-group = one work item (a contiguous range of the samples of one
 // tile, in sorted order) and one group of CG = NW * LPC * CW coils.  Lane l
 // of a wave owns tap l % NTAPS of the current sample for CW coils of the
@@ -331,7 +428,10 @@ enum { SRC_VALS = 0, SRC_DATA = 1 };
 // item group's values (cb coils per row); with SRC_DATA the caller's data
 // row orig (coils c0 .. at leading dimension ldc), scaled by sqrt(w)
 // (folded into the staged x weights).
-template <int NDIM, int NW, int CW, int SRC>
+// With RW the batch runs through rw_batch (kernel weights in registers,
+// values by DPP row broadcasts; every row of 16 lanes is one coil slot in
+// 2D, so a row broadcast hands each slot its own coil's value).
+template <int NDIM, int NW, int CW, int SRC, bool RW = false>
 __global__ __launch_bounds__(64 * NW) void k_spread_items(
     const float2* __restrict__ V, int ldc, int c0, int cb, const SampleRec* __restrict__ rec,
     const GridItem* __restrict__ items, int item0, int ntx, int nty,
@@ -351,6 +451,7 @@ __global__ __launch_bounds__(64 * NW) void k_spread_items(
   float* sim = sre + SB * 2 * CG;
   __shared__ int s_rs[SB];  // run starts of the staged batch
   __shared__ int s_nr;
+  __shared__ unsigned s_sm[2];  // the run starts as a bit mask (RW)
 
   const int ng = (cb + CG - 1) / CG;
   int item, g;
@@ -370,9 +471,9 @@ __global__ __launch_bounds__(64 * NW) void k_spread_items(
   const int q0 = (wave * H::LPC + cslot) * CW;  // first group coil of this lane
   // waves whose coils all lie beyond the chunk only help with the staging
   const bool active = (wave * H::LPC) * CW < cga;
-  float2 racc[CW];
+  float2 racc[CW], rbase[CW];
 #pragma unroll
-  for (int q = 0; q < CW; ++q) racc[q] = make_float2(0.f, 0.f);
+  for (int q = 0; q < CW; ++q) racc[q] = rbase[q] = make_float2(0.f, 0.f);
   int rkey = -1, raddr = 0;
 
   // staging, double-buffered through registers: thread t < SB fetches the
@@ -436,9 +537,34 @@ __global__ __launch_bounds__(64 * NW) void k_spread_items(
       const bool start = tid < n && pkey != (tid > 0 ? prev : rkey);
       const unsigned long long mask = __ballot(start);
       if (start) s_rs[__popcll(mask & ((1ull << tid) - 1ull))] = tid;
-      if (tid == 0) s_nr = __popcll(mask);
+      if (tid == 0) {
+        s_nr = __popcll(mask);
+        s_sm[0] = (unsigned)mask;
+        s_sm[1] = (unsigned)(mask >> 32);
+      }
     }
     __syncthreads();
+    if constexpr (RW) {
+      static_assert(SB == 64, "one run-start bit per sample");
+      // chunk c of 16 samples: sample 16 c + (lane & 15) of this lane's coil
+      float2 cr[CW][4], cv[CW];
+#pragma unroll
+      for (int q = 0; q < CW; ++q) {
+        cv[q] = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int e = 2 * ((16 * c + (lane & 15)) * CG + q0 + q);
+          cr[q][c] = make_float2(sre[e], sim[e]);
+        }
+      }
+      const int vkey = __float_as_int(srec[lane * SRP]);
+      const unsigned sm0 = __builtin_amdgcn_readfirstlane(s_sm[0]),
+                     sm1 = __builtin_amdgcn_readfirstlane(s_sm[1]);
+      if (k0 + SB < kend) prefetch(k0 + SB, min(SB, kend - k0 - SB));
+      rw_batch<NDIM, CW, true>(acc, srec, n, sm0, sm1, vkey, q0, loff, dx, dy, dz, active, cr,
+                               cv, racc, rbase, rkey, raddr);
+      continue;
+    }
     if (k0 + SB < kend) prefetch(k0 + SB, min(SB, kend - k0 - SB));
     // the run bounds are the same for every lane: reading them through
     // readfirstlane keeps the loop control in scalar registers
@@ -484,8 +610,13 @@ __global__ __launch_bounds__(64 * NW) void k_spread_items(
 #pragma unroll
     for (int q = 0; q < CW; ++q) {
       float* pl = acc + (size_t)(q0 + q) * 2 * H::PLANE + raddr;
-      pl[0] += racc[q].x;
-      pl[H::PLANE] += racc[q].y;
+      if constexpr (RW) {
+        pl[0] = rbase[q].x + racc[q].x;
+        pl[H::PLANE] = rbase[q].y + racc[q].y;
+      } else {
+        pl[0] += racc[q].x;
+        pl[H::PLANE] += racc[q].y;
+      }
     }
   }
   __syncthreads();
@@ -501,26 +632,6 @@ __global__ __launch_bounds__(64 * NW) void k_spread_items(
       d[q] = make_float2(acc[(size_t)q * 2 * H::PLANE + a],
                          acc[(size_t)q * 2 * H::PLANE + H::PLANE + a]);
   }
-}
-
-// f(std::integral_constant<int, i>) for i = 0 .. N-1, expanded at compile time
-template <class F, int... I>
-__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, I...>) {
-  (f(std::integral_constant<int, I>{}), ...);
-}
-template <int N, class F>
-__device__ __forceinline__ void static_for(F& f) {
-  static_for_impl(f, std::make_integer_sequence<int, N>{});
-}
-
-// acc += src[lane j of this lane's row of 16] * w: a VOP2 FMA whose first
-// operand is read through the row broadcast of DPP (row_newbcast, CDNA3 and
-// later), so a value is broadcast and used in one instruction
-template <int J>
-__device__ __forceinline__ void fmac_rowbcast(float& acc, float src, float w) {
-  asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
-               : "+v"(acc)
-               : "v"(src), "v"(w), "n"(J));
 }
 
 // The 3D spreading of the normal operator with the sample values held in
@@ -656,64 +767,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
       const unsigned sm0 = __builtin_amdgcn_readfirstlane(s_sm[0]),
                      sm1 = __builtin_amdgcn_readfirstlane(s_sm[1]);
       if (k0 + SB < kend) prefetch(k0 + SB, min(SB, kend - k0 - SB));
-      // rows s >= n hold stale records: their weights are formed, never
-      // used.  All reads are issued before the first product; the empty asm
-      // statements keep the products ahead of the sample loop (rather than
-      // inside its run branches)
-      float wr[SB];
-#pragma unroll
-      for (int s = 0; s < SB; ++s) {
-        const float* d = srec + s * SRP;
-        wr[s] = d[1 + dx] * d[5 + dy + 4 * dz];
-      }
-#pragma unroll
-      for (int s = 0; s < SB; ++s) asm volatile("" : "+v"(wr[s]));
-      if (active) {
-        // one step per sample, expanded at compile time (the broadcast lane
-        // and the weight register are constants of each step)
-        auto step = [&](auto sc) {
-          constexpr int s = decltype(sc)::value;
-          if (s >= n) return;
-          if (((s < 32 ? sm0 : sm1) >> (s & 31)) & 1u) {
-            // the LDS value of the run's voxel was read when the run opened
-            // (a run's voxels are this lane's alone until it flushes), so
-            // the flush rarely waits
-            if (rkey >= 0) {
-#pragma unroll
-              for (int q = 0; q < CW; ++q) {
-                float* pl = acc + (size_t)(q0 + q) * 2 * H::PLANE + raddr;
-                pl[0] = rbase[q].x + racc[q].x;
-                pl[H::PLANE] = rbase[q].y + racc[q].y;
-                racc[q] = make_float2(0.f, 0.f);
-              }
-            }
-            rkey = __builtin_amdgcn_readlane(vkey, s);
-            raddr = __builtin_amdgcn_readfirstlane((rkey >> 16) * H::PZ +
-                                                   ((rkey >> 8) & 0xff) * H::PY +
-                                                   (rkey & 0xff)) + loff;
-#pragma unroll
-            for (int q = 0; q < CW; ++q) {
-              const float* pl = acc + (size_t)(q0 + q) * 2 * H::PLANE + raddr;
-              rbase[q] = make_float2(pl[0], pl[H::PLANE]);
-            }
-          }
-#pragma unroll
-          for (int q = 0; q < CW; ++q) {
-            if constexpr (VAR == 3) {
-              fmac_rowbcast<(s & 15)>(racc[q].x, cr[q][s >> 4].x, wr[s]);
-              fmac_rowbcast<(s & 15)>(racc[q].y, cr[q][s >> 4].y, wr[s]);
-            } else {
-              const float vr =
-                  __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cv[q].x), s));
-              const float vi =
-                  __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cv[q].y), s));
-              racc[q].x += wr[s] * vr;
-              racc[q].y += wr[s] * vi;
-            }
-          }
-        };
-        static_for<SB>(step);
-      }
+      rw_batch<3, CW, VAR == 3>(acc, srec, n, sm0, sm1, vkey, q0, loff, dx, dy, dz, active,
+                                cr, cv, racc, rbase, rkey, raddr);
       continue;
     }
     // lane j: key of sample j and start of run j of the batch (broadcast
@@ -920,9 +975,12 @@ int spread_items_launch(cs_ctx* c, int src, const float2* vals, int ldc, int c0,
                         : spread_lds_bytes<NDIM, NW, CW>();
   if (lds > 160 * 1024) return fail(c, CS_EINVAL, "spread tile does not fit in LDS");
   if (nitems <= 0) return CS_OK;
+  // shapes 9-12 (VAR 2, 3) take the register-weight loop in both kernels
+  // (k_spread_items always with the DPP broadcasts)
+  constexpr bool rw = VAR >= 2;
   auto kern = rl ? k_spread_rl<NW, CW, VAR>
-                 : (src == SRC_VALS ? k_spread_items<NDIM, NW, CW, SRC_VALS>
-                                    : k_spread_items<NDIM, NW, CW, SRC_DATA>);
+                 : (src == SRC_VALS ? k_spread_items<NDIM, NW, CW, SRC_VALS, rw>
+                                    : k_spread_items<NDIM, NW, CW, SRC_DATA, rw>);
   if (lds > 64 * 1024)
     CS_HIP(c, hipFuncSetAttribute((const void*)kern,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -1280,10 +1338,12 @@ int setup_noncart(cs_ctx* c, const float* coords_dev, const float* dcf_dev) {
                              c->stream));
   }
 
-  // work items: each tile's samples in chunks of at most `chunk`; the slot of
-  // an item is its index in tile order, so the slots of tile t are
-  // item_off[t] .. item_off[t + 1]
-  const long long chunk = 2048;
+  // work items: each tile's samples in chunks of at most `chunk` (2048 in 3D;
+  // 512 in 2D, where a slice has few tiles and the heaviest items set the
+  // launch time); the slot of an item is its index in tile order, so the
+  // slots of tile t are item_off[t] .. item_off[t + 1]
+  long long chunk = nd == 3 ? 2048 : 512;
+  if (const char* e = std::getenv("CS_ITEM_SAMPLES")) chunk = std::max(64LL, std::atoll(e));
   std::vector<GridItem> items;
   std::vector<int> ioff(c->ntiles + 1, 0);
   for (long long t = 0; t < c->ntiles; ++t) {
