@@ -59,6 +59,15 @@ struct PassArgs {
   int xcd;               // 1: each XCD takes a contiguous range of panels
 };
 
+// Work-groups are dealt to the 8 XCDs in turn (group b to XCD b mod 8), and
+// each XCD has an L2 of its own.  This order gives XCD x a contiguous range
+// of the logical groups instead, so that groups whose data are neighbours in
+// memory (sharing cache lines) run on the same L2.  A bijection on [0, G).
+__device__ __forceinline__ long long xcd_contiguous(long long b, long long G) {
+  const long long q = G >> 3, r = G & 7, x = b & 7, i = b >> 3;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 // Sample record of the sorted non-Cartesian trajectory (64 bytes): first tap
 // relative to the tile's origin (x | y << 8 | z << 16), density weight w and
 // sqrt(w), index in the caller's order, and the four kernel weights per axis.
@@ -109,6 +118,7 @@ struct cs_ctx {
   int fft_pix = 1, fft_cols = 16;
   int fft_xcd = 1;                // XCD-contiguous panel order in the FFT passes
   int grid_xcd = 1;               // gridding: an item's coil groups on one XCD
+  int merge_xcd = 0;              // merge: each XCD a contiguous range of tiles
 
   // operator
   const float2* maps = nullptr;   // borrowed [D][C]

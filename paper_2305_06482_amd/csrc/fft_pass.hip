@@ -317,15 +317,6 @@ __device__ __forceinline__ void fft_panel(float2* buf, const float2* tw, int tr,
     fft_stages<L, TC, 0, 1, 1>(buf, tw, tr, tc);
 }
 
-// Work-groups are dealt to the 8 XCDs in turn (group b to XCD b mod 8), and
-// each XCD has an L2 of its own.  This order gives XCD x a contiguous range
-// of the logical groups instead, so that panels next to each other in memory
-// (sharing cache lines) run on the same L2.  A bijection on [0, G).
-__device__ __forceinline__ long long xcd_contiguous(long long b, long long G) {
-  const long long q = G >> 3, r = G & 7, x = b & 7, i = b >> 3;
-  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
-}
-
 template <int L, int TC>
 __global__ __launch_bounds__(256) void k_pass_t(PassArgs a) {
   constexpr int TR = pass_rows<TC>();
@@ -335,6 +326,7 @@ __global__ __launch_bounds__(256) void k_pass_t(PassArgs a) {
   float2* tw = smem + L * TC;     // [L]
   const int tid = threadIdx.x;
   const int tc = tid % TC, tr = tid / TC;
+  // panels next to each other in memory (sharing cache lines) on one L2
   const long long blk = a.xcd ? xcd_contiguous(blockIdx.x, gridDim.x) : (long long)blockIdx.x;
   const long long outer = blk / a.nblk;
   const long long col0 = (blk - outer * a.nblk) * a.Wt;

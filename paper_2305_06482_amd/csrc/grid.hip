@@ -370,10 +370,13 @@ __device__ __forceinline__ void rw_batch(float* acc, const float* srec, int n, u
   for (int s = 0; s < SB; ++s) asm volatile("" : "+v"(wr[s]));
   if (!active) return;
   // one step per sample, expanded at compile time (the broadcast lane
-  // and the weight register are constants of each step)
-  auto step = [&](auto sc) {
+  // and the weight register are constants of each step); a full batch
+  // (the usual case) runs a copy without the per-sample bound test
+  auto step = [&](auto sc, auto fc) {
     constexpr int s = decltype(sc)::value;
-    if (s >= n) return;
+    if constexpr (!decltype(fc)::value) {
+      if (s >= n) return;
+    }
     if (((s < 32 ? sm0 : sm1) >> (s & 31)) & 1u) {
       // the LDS value of the run's voxel was read when the run opened
       // (a run's voxels are this lane's alone until it flushes), so
@@ -412,7 +415,14 @@ __device__ __forceinline__ void rw_batch(float* acc, const float* srec, int n, u
       }
     }
   };
-  static_for<SB>(step);
+  auto run = [&](auto fc) {
+    auto one = [&](auto sc) { step(sc, fc); };
+    static_for<SB>(one);
+  };
+  if (n == SB)
+    run(std::true_type{});
+  else
+    run(std::false_type{});
 }
 
 // One work-group = one work item (a contiguous range of the samples of one
@@ -896,13 +906,14 @@ __device__ __forceinline__ int halo_cover(int g, int ig, int nt, int T, int m, i
 template <int NDIM, int CG>
 __global__ __launch_bounds__(256) void k_spread_merge(
     const float2* __restrict__ P, const int* __restrict__ item_off, int cb, int ng, int ntx,
-    int nty, int ntz, int mx, int my, int mz, float2* __restrict__ G) {
+    int nty, int ntz, int mx, int my, int mz, float2* __restrict__ G, int xcd) {
   using H = Halo<NDIM>;
   constexpr int TV = H::TX * H::TY * H::TZ;
   constexpr int BPT = (TV + 255) / 256;  // blocks per tile
   constexpr int NGMAX = (kCoilChunk + CG - 1) / CG;
-  const int tile = blockIdx.x / BPT;
-  const int v = (blockIdx.x - tile * BPT) * 256 + threadIdx.x;
+  const int b = xcd ? (int)xcd_contiguous(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int tile = b / BPT;
+  const int v = (b - tile * BPT) * 256 + threadIdx.x;
   if (v >= TV) return;
   const int ix = tile % ntx, iy = (tile / ntx) % nty, iz = tile / (ntx * nty);
   const int gx = ix * H::TX + v % H::TX, gy = iy * H::TY + (v / H::TX) % H::TY,
@@ -1001,7 +1012,7 @@ int merge_launch(cs_ctx* c, int cb, float2* grid) {
   if (blocks > 0x7fffffffLL) return fail(c, CS_EINVAL, "spread merge grid too large");
   CS_KLAUNCH(c, K_MERGE, (k_spread_merge<NDIM, CG>), dim3((unsigned)blocks), dim3(256), 0,
              c->stream, c->partial, c->item_off, cb, ng, c->ntile[2], c->ntile[1],
-             c->ntile[0], c->mx, c->my, c->mz, grid);
+             c->ntile[0], c->mx, c->my, c->mz, grid, c->merge_xcd);
   CS_HIP(c, hipGetLastError());
   return CS_OK;
 }
@@ -1254,8 +1265,9 @@ int setup_noncart(cs_ctx* c, const float* coords_dev, const float* dcf_dev) {
   const char* cfg = std::getenv("CS_SPREAD_CFG");
   c->spread_cfg = cfg ? std::atoi(cfg) : kSpreadDefault;
   if (const char* e = std::getenv("CS_GRID_XCD")) c->grid_xcd = std::atoi(e) != 0;
+  if (const char* e = std::getenv("CS_MERGE_XCD")) c->merge_xcd = std::atoi(e) != 0;
   const char* icfg = std::getenv("CS_INTERP_CFG");
-  c->interp_cfg = icfg ? std::atoi(icfg) : 1;
+  c->interp_cfg = icfg ? std::atoi(icfg) : 3;
   // samples per item group of the normal operator (CS_GROUP_SAMPLES in the
   // environment; at least one work item)
   const char* gcfg = std::getenv("CS_GROUP_SAMPLES");
