@@ -371,7 +371,7 @@ int cs_autotune_spread(cs_ctx* ctx, const void* maps, int ncoil, int reps, int* 
  * CS_INTERP_NCFG)): 0 gathers every tap of a sample from the grid in global
  * memory; 1, 2 and 3 (the default) copy each work item's halo'd grid tile
  * into LDS first and gather from there, for coil groups of at most 8 (1), 12
- * (2) or 4 (3) coils in 3D; 4 is 1 with the tile's (re, im) pairs
+ * (2) or 4 (3) coils in 3D; 4 is 3 with the tile's (re, im) pairs
  * interleaved in LDS (one 8-byte read per tap and coil).  All sum the taps in
  * the same order.  The
  * environment variable CS_INTERP_CFG sets the default of new operators. */

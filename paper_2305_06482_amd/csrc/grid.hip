@@ -191,14 +191,16 @@ __global__ __launch_bounds__(NT) void k_interp_items(
 #pragma unroll
     for (int q = 0; q < CG; ++q) acc[q] = make_float2(0.f, 0.f);
     const int nzt = NDIM == 3 ? 4 : 1;
-    // one row of four x taps per step: unrolling further lets the compiler
-    // hoist the reads of many rows and run out of registers.  The row
-    // weights are picked by selects: indexing the weight arrays with a loop
-    // counter would put them in scratch memory.
+    // one row of four x taps per step (two rows for groups of at most 4
+    // coils): unrolling further lets the compiler hoist the reads of many
+    // rows and run out of registers.  The row weights are picked by selects:
+    // indexing the weight arrays with a loop counter would put them in
+    // scratch memory.
+    constexpr int UY = CG <= 4 ? 2 : 1;
 #pragma unroll 1
     for (int dz = 0; dz < nzt; ++dz) {
       const float wzv = NDIM == 3 ? sel4(r.wz, dz) : 1.f;
-#pragma unroll 1
+#pragma unroll UY
       for (int dy = 0; dy < 4; ++dy) {
         const float wyz = wzv * sel4(r.wy, dy);
         if constexpr (TILE) {
@@ -287,7 +289,7 @@ int interp_dispatch(cs_ctx* c, const float2* grid, int cb, int item0, int nitems
                     float2* out, int ldc, int c0, int caller_order) {
   const bool tile = c->interp_cfg >= 1;
   const bool il = c->interp_cfg == 4;  // interleaved (re, im) LDS tile
-  int cmax = c->interp_cfg == 2 ? 12 : (c->interp_cfg == 3 ? 4 : 8);
+  int cmax = c->interp_cfg == 2 ? 12 : (c->interp_cfg >= 3 ? 4 : 8);
   if (NDIM == 2) cmax = 16;
   const int ng = (cb + cmax - 1) / cmax;
   const int cg = (cb + ng - 1) / ng;
@@ -347,13 +349,14 @@ __device__ __forceinline__ void fmac_rowbcast(float& acc, float src, float w) {
 // Values: with DPP chunk c of 16 samples in cr[q][c] (sample 16 c + j in
 // lane j of every row of 16), else sample j's in lane j of cv[q].  Lanes
 // beyond the staged rows form weights from stale records, never used.
+// lacc = this lane's tap of its first coil plane at the tile origin; rp =
+// the open run's voxel in that plane (coil q at rp + 2 q PLANE).
 template <int NDIM, int CW, bool DPP>
-__device__ __forceinline__ void rw_batch(float* acc, const float* srec, int n, unsigned sm0,
-                                         unsigned sm1, int vkey, int q0, int loff, int dx,
-                                         int dy, int dz, bool active,
-                                         const float2 (&cr)[CW][4], const float2 (&cv)[CW],
-                                         float2 (&racc)[CW], float2 (&rbase)[CW], int& rkey,
-                                         int& raddr) {
+__device__ __forceinline__ void rw_batch(float* lacc, const float* srec, int n, unsigned sm0,
+                                         unsigned sm1, int vkey, int dx, int dy, int dz,
+                                         bool active, const float2 (&cr)[CW][4],
+                                         const float2 (&cv)[CW], float2 (&racc)[CW],
+                                         float2 (&rbase)[CW], int& rkey, float*& rp) {
   using H = Halo<NDIM>;
   constexpr int SB = kSpreadBatch, SRP = kSpreadRecPitch;
   // rows s >= n hold stale records: their weights are formed, never
@@ -381,22 +384,25 @@ __device__ __forceinline__ void rw_batch(float* acc, const float* srec, int n, u
       // the LDS value of the run's voxel was read when the run opened
       // (a run's voxels are this lane's alone until it flushes), so
       // the flush rarely waits
-      if (rkey >= 0) {
-#pragma unroll
-        for (int q = 0; q < CW; ++q) {
-          float* pl = acc + (size_t)(q0 + q) * 2 * H::PLANE + raddr;
-          pl[0] = rbase[q].x + racc[q].x;
-          pl[H::PLANE] = rbase[q].y + racc[q].y;
-          racc[q] = make_float2(0.f, 0.f);
-        }
-      }
-      rkey = __builtin_amdgcn_readlane(vkey, s);
-      raddr = __builtin_amdgcn_readfirstlane((rkey >> 16) * H::PZ +
-                                             ((rkey >> 8) & 0xff) * H::PY +
-                                             (rkey & 0xff)) + loff;
+      // no test for an open run: before the item's first run rp is the
+      // tile origin of this lane's tap and rbase = racc = 0, and the LDS tile
+      // is still all zero there, so that flush writes 0 over 0 (one code path
+      // also spares the wait that the merge of two paths would put before
+      // the next run's reads)
 #pragma unroll
       for (int q = 0; q < CW; ++q) {
-        const float* pl = acc + (size_t)(q0 + q) * 2 * H::PLANE + raddr;
+        float* pl = rp + (size_t)q * 2 * H::PLANE;
+        pl[0] = rbase[q].x + racc[q].x;
+        pl[H::PLANE] = rbase[q].y + racc[q].y;
+        racc[q] = make_float2(0.f, 0.f);
+      }
+      rkey = __builtin_amdgcn_readlane(vkey, s);
+      // the run's first tap is uniform: a scalar offset, one vector add
+      rp = lacc + __builtin_amdgcn_readfirstlane((rkey >> 16) * H::PZ +
+                                                 ((rkey >> 8) & 0xff) * H::PY + (rkey & 0xff));
+#pragma unroll
+      for (int q = 0; q < CW; ++q) {
+        const float* pl = rp + (size_t)q * 2 * H::PLANE;
         rbase[q] = make_float2(pl[0], pl[H::PLANE]);
       }
     }
@@ -485,6 +491,8 @@ __global__ __launch_bounds__(64 * NW) void k_spread_items(
 #pragma unroll
   for (int q = 0; q < CW; ++q) racc[q] = rbase[q] = make_float2(0.f, 0.f);
   int rkey = -1, raddr = 0;
+  float* const lacc = acc + (size_t)q0 * 2 * H::PLANE + loff;  // RW run addressing
+  float* rp = lacc;
 
   // staging, double-buffered through registers: thread t < SB fetches the
   // record of sample t of the batch; value e = t + j NT is (sample e / CG,
@@ -571,8 +579,8 @@ __global__ __launch_bounds__(64 * NW) void k_spread_items(
       const unsigned sm0 = __builtin_amdgcn_readfirstlane(s_sm[0]),
                      sm1 = __builtin_amdgcn_readfirstlane(s_sm[1]);
       if (k0 + SB < kend) prefetch(k0 + SB, min(SB, kend - k0 - SB));
-      rw_batch<NDIM, CW, true>(acc, srec, n, sm0, sm1, vkey, q0, loff, dx, dy, dz, active, cr,
-                               cv, racc, rbase, rkey, raddr);
+      rw_batch<NDIM, CW, true>(lacc, srec, n, sm0, sm1, vkey, dx, dy, dz, active, cr, cv, racc,
+                               rbase, rkey, rp);
       continue;
     }
     if (k0 + SB < kend) prefetch(k0 + SB, min(SB, kend - k0 - SB));
@@ -619,7 +627,8 @@ __global__ __launch_bounds__(64 * NW) void k_spread_items(
   if (rkey >= 0) {
 #pragma unroll
     for (int q = 0; q < CW; ++q) {
-      float* pl = acc + (size_t)(q0 + q) * 2 * H::PLANE + raddr;
+      float* pl = RW ? rp + (size_t)q * 2 * H::PLANE
+                     : acc + (size_t)(q0 + q) * 2 * H::PLANE + raddr;
       if constexpr (RW) {
         pl[0] = rbase[q].x + racc[q].x;
         pl[H::PLANE] = rbase[q].y + racc[q].y;
@@ -702,6 +711,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
 #pragma unroll
   for (int q = 0; q < CW; ++q) racc[q] = rbase[q] = make_float2(0.f, 0.f);
   int rkey = -1, raddr = 0;
+  float* const lacc = acc + (size_t)q0 * 2 * H::PLANE + loff;  // VAR >= 2 run addressing
+  float* rp = lacc;
 
   // thread t < SB fetches the record of sample t of the next batch; lane j of
   // every wave fetches sample j's values of the wave's coils, which pass
@@ -777,8 +788,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
       const unsigned sm0 = __builtin_amdgcn_readfirstlane(s_sm[0]),
                      sm1 = __builtin_amdgcn_readfirstlane(s_sm[1]);
       if (k0 + SB < kend) prefetch(k0 + SB, min(SB, kend - k0 - SB));
-      rw_batch<3, CW, VAR == 3>(acc, srec, n, sm0, sm1, vkey, q0, loff, dx, dy, dz, active,
-                                cr, cv, racc, rbase, rkey, raddr);
+      rw_batch<3, CW, VAR == 3>(lacc, srec, n, sm0, sm1, vkey, dx, dy, dz, active, cr, cv,
+                                racc, rbase, rkey, rp);
       continue;
     }
     // lane j: key of sample j and start of run j of the batch (broadcast
@@ -855,7 +866,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
   if (rkey >= 0) {
 #pragma unroll
     for (int q = 0; q < CW; ++q) {
-      float* pl = acc + (size_t)(q0 + q) * 2 * H::PLANE + raddr;
+      float* pl = VAR >= 2 ? rp + (size_t)q * 2 * H::PLANE
+                           : acc + (size_t)(q0 + q) * 2 * H::PLANE + raddr;
       if constexpr (PF) {
         pl[0] = rbase[q].x + racc[q].x;
         pl[H::PLANE] = rbase[q].y + racc[q].y;

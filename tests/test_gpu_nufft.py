@@ -98,7 +98,7 @@ def test_normal_is_deterministic():
                                     ("cones", 12), ("cones", 32)])
 def test_interp_variants_agree(kind, C):
     """The global-memory gather (variant 0) and the LDS-tile interpolation
-    (variants 1, 2, 3: coil groups of 8, 12, 4; 4: variant 1 with the tile
+    (variants 1, 2, 3: coil groups of 8, 12, 4; 4: variant 3 with the tile
     interleaved as (re, im) pairs) against the oracle and
     against each other: same taps, same summation order.  Shapes with partial edge tiles (grid 30 = 3 x 8 + 6),
     odd coil counts (guarded group lanes), a grid shorter than the tile and
