@@ -115,7 +115,7 @@ struct cs_ctx {
   std::map<int, cs::FFTPlan> plans;
   // FFT pass panels: pixels per panel of an image pass (all coils of each)
   // and columns per panel of a grid pass (CS_FFT_PIX / CS_FFT_COLS)
-  int fft_pix = 1, fft_cols = 16;
+  int fft_pix = 1, fft_cols = 12;
   int fft_xcd = 1;                // XCD-contiguous panel order in the FFT passes
   int grid_xcd = 1;               // gridding: an item's coil groups on one XCD
   int merge_xcd = 0;              // merge: each XCD a contiguous range of tiles
