@@ -341,26 +341,48 @@ __global__ __launch_bounds__(256) void k_pass_t(PassArgs a) {
     for (int r = tr; r < L; r += TR) buf[r * TC + tc] = make_float2(0.f, 0.f);
   __syncthreads();
 
+  // rows t = tr + i TR, i < NR: a thread's rows are loaded in one unrolled
+  // sweep (every load issued before the first wait) and then stored to LDS
+  constexpr int NR = (L + TR - 1) / TR;
   if (colok) {
     const uint8_t* mrow = a.premask ? a.mask + outer * a.mask_os : nullptr;
+    float2 v[NR];
     if (a.prologue == PRO_IMAGE) {
       const float dpv = a.dp[p];
-      for (int t = tr; t < a.n_in; t += TR) {
-        const long long pix = (long long)t * a.P + p;
-        float2 v = cscale(cmul(a.img[pix], a.maps[pix * a.maps_ldc + a.maps_c0 + c]),
-                          a.da[t] * dpv);
-        if (mrow && mrow[(long long)t * a.mask_rs] == 0) v = make_float2(0.f, 0.f);
-        const int row = a.pad_in ? wrap_row(t, a.n_in, L) : t;
-        buf[row * TC + tc] = v;
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        const int t = tr + i * TR;
+        v[i] = make_float2(0.f, 0.f);
+        if (t < a.n_in) {
+          const long long pix = (long long)t * a.P + p;
+          v[i] = cscale(cmul(a.img[pix], a.maps[pix * a.maps_ldc + a.maps_c0 + c]),
+                        a.da[t] * dpv);
+        }
       }
     } else {
       const float2* src = a.src + outer * a.src_os + p * a.src_ldc + a.src_c0 + c;
-      for (int t = tr; t < a.n_in; t += TR) {
-        float2 v = src[(long long)t * a.src_rs];
-        if (mrow && mrow[(long long)t * a.mask_rs] == 0) v = make_float2(0.f, 0.f);
-        const int row = a.pad_in ? wrap_row(t, a.n_in, L) : t;
-        buf[row * TC + tc] = v;
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        const int t = tr + i * TR;
+        v[i] = t < a.n_in ? src[(long long)t * a.src_rs] : make_float2(0.f, 0.f);
       }
+    }
+    if (mrow) {
+      // the mask bytes of all rows, then the zeroing (no load waits between)
+      uint8_t mk[NR];
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        const int t = tr + i * TR;
+        mk[i] = t < a.n_in ? mrow[(long long)t * a.mask_rs] : (uint8_t)1;
+      }
+#pragma unroll
+      for (int i = 0; i < NR; ++i)
+        if (mk[i] == 0) v[i] = make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int t = tr + i * TR;
+      if (t < a.n_in) buf[(a.pad_in ? wrap_row(t, a.n_in, L) : t) * TC + tc] = v[i];
     }
   }
   __syncthreads();
@@ -376,18 +398,48 @@ __global__ __launch_bounds__(256) void k_pass_t(PassArgs a) {
   }
 
   if (a.epilogue == EPI_IMAGE) {
+    // every (pixel, coil) thread forms conj(c_j) times its rows' values in
+    // place (map loads of all rows issued together), then the pixel's first
+    // thread sums its coils in order
+    if (colok) {
+      float2 m[NR];
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        const int t = tr + i * TR;
+        m[i] = make_float2(0.f, 0.f);
+        if (t < a.n_out) m[i] = a.maps[((long long)t * a.P + p) * a.maps_ldc + a.maps_c0 + c];
+      }
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        const int t = tr + i * TR;
+        if (t < a.n_out) {
+          float2* rv = buf + (a.pad_out ? wrap_row(t, a.n_out, L) : t) * TC + tc;
+          *rv = cmulc(m[i], *rv);
+        }
+      }
+    }
+    __syncthreads();
     if (colok && c == 0) {
       const float dpv = a.dp[p];
-      for (int t = tr; t < a.n_out; t += TR) {
-        const int row = a.pad_out ? wrap_row(t, a.n_out, L) : t;
-        const long long pix = (long long)t * a.P + p;
-        const float2* mp = a.maps + pix * a.maps_ldc + a.maps_c0;
-        const float2* rv = buf + row * TC + tc;
-        float2 acc = make_float2(0.f, 0.f);
-        for (int cc = 0; cc < a.cb; ++cc) acc = cadd(acc, cmulc(mp[cc], rv[cc]));
-        acc = cscale(acc, a.da[t] * dpv);
-        if (a.accumulate) acc = cadd(acc, a.img_out[pix]);
-        a.img_out[pix] = acc;
+      float2 prev[NR];
+      if (a.accumulate) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+          const int t = tr + i * TR;
+          prev[i] = t < a.n_out ? a.img_out[(long long)t * a.P + p] : make_float2(0.f, 0.f);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        const int t = tr + i * TR;
+        if (t < a.n_out) {
+          const float2* rv = buf + (a.pad_out ? wrap_row(t, a.n_out, L) : t) * TC + tc;
+          float2 acc = make_float2(0.f, 0.f);
+          for (int cc = 0; cc < a.cb; ++cc) acc = cadd(acc, rv[cc]);
+          acc = cscale(acc, a.da[t] * dpv);
+          if (a.accumulate) acc = cadd(acc, prev[i]);
+          a.img_out[(long long)t * a.P + p] = acc;
+        }
       }
     }
   } else if (colok) {
