@@ -152,40 +152,59 @@ __global__ __launch_bounds__(NT) void k_interp_items(
   const int ix = tile % ntx, iy = (tile / ntx) % nty, iz = tile / (ntx * nty);
   const int x0 = ix * H::TX, y0 = iy * H::TY, z0 = iz * H::TZ;
   const int tid = threadIdx.x;
+  // this thread's first sample record, requested before the tile so that
+  // the two loads overlap
+  SampleRec r0;
+  if (kbeg + tid < kend) r0 = rec[kbeg + tid];
   if constexpr (TILE) {
     // one thread per voxel of the halo'd tile copies the group's coils, so
-    // the index arithmetic is paid once per voxel
-    for (int e = tid; e < H::EXT; e += NT) {
-      const int lx = e % H::EX, ly = (e / H::EX) % H::EY, lz = e / (H::EX * H::EY);
-      // wrap into the grid by subtraction (a runtime modulo costs dozens of
-      // instructions): the coordinate is below m + EX - 1 and the grid is at
-      // least 4 long per axis, so (EX + 3) / 4 subtractions suffice
-      int gx = x0 + lx, gy = y0 + ly, gz = NDIM == 3 ? z0 + lz : 0;
+    // the index arithmetic is paid once per voxel; a thread's voxels are
+    // loaded in one unrolled sweep, then stored to LDS
+    constexpr int NE = (H::EXT + NT - 1) / NT;
+    float2 tv[NE][CG];
+    int ta[NE];
 #pragma unroll
-      for (int w = 0; w < (H::EX + 3) / 4; ++w) {
-        gx -= gx >= mx ? mx : 0;
-        gy -= gy >= my ? my : 0;
-        if (NDIM == 3) gz -= gz >= mz ? mz : 0;
+    for (int i = 0; i < NE; ++i) {
+      const int e = tid + i * NT;
+      ta[i] = -1;
+      if (e < H::EXT) {
+        const int lx = e % H::EX, ly = (e / H::EX) % H::EY, lz = e / (H::EX * H::EY);
+        // wrap into the grid by subtraction (a runtime modulo costs dozens
+        // of instructions): the coordinate is below m + EX - 1 and the grid
+        // is at least 4 long per axis, so (EX + 3) / 4 subtractions suffice
+        int gx = x0 + lx, gy = y0 + ly, gz = NDIM == 3 ? z0 + lz : 0;
+#pragma unroll
+        for (int w = 0; w < (H::EX + 3) / 4; ++w) {
+          gx -= gx >= mx ? mx : 0;
+          gy -= gy >= my ? my : 0;
+          if (NDIM == 3) gz -= gz >= mz ? mz : 0;
+        }
+        const float2* src = G + (((long long)gz * my + gy) * mx + gx) * cb + cg0;
+        ta[i] = lz * H::PZ + ly * H::PY + lx;
+#pragma unroll
+        for (int q = 0; q < CG; ++q) tv[i][q] = q < cga ? src[q] : make_float2(0.f, 0.f);
       }
-      const float2* src = G + (((long long)gz * my + gy) * mx + gx) * cb + cg0;
-      const int a = lz * H::PZ + ly * H::PY + lx;
+    }
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      if (ta[i] < 0) continue;
+      const int a = ta[i];
 #pragma unroll
       for (int q = 0; q < CG; ++q) {
-        float2 v = make_float2(0.f, 0.f);
-        if (q < cga) v = src[q];
         if constexpr (IL) {
           // interleaved (re, im) per voxel: one 8-byte LDS read per tap
-          reinterpret_cast<float2*>(lds)[(size_t)q * H::PLANE + a] = v;
+          reinterpret_cast<float2*>(lds)[(size_t)q * H::PLANE + a] = tv[i][q];
         } else {
-          lds[(size_t)q * 2 * H::PLANE + a] = v.x;
-          lds[(size_t)q * 2 * H::PLANE + H::PLANE + a] = v.y;
+          lds[(size_t)q * 2 * H::PLANE + a] = tv[i][q].x;
+          lds[(size_t)q * 2 * H::PLANE + H::PLANE + a] = tv[i][q].y;
         }
       }
     }
     __syncthreads();
   }
+  SampleRec r = r0;
   for (int k = kbeg + tid; k < kend; k += NT) {
-    const SampleRec r = rec[k];
+    if (k != kbeg + tid) r = rec[k];
     const int lx = r.key & 0xff, ly = (r.key >> 8) & 0xff, lz = r.key >> 16;
     float2 acc[CG];
 #pragma unroll
