@@ -85,12 +85,18 @@ KERNEL_LAUNCHES_PER_APPLY = {"fft_pass": 6}
 
 
 def kernel_bytes(geom, cb):
-    """Algorithmic bytes per launch of the main kernels for a coil chunk cb."""
+    """Algorithmic bytes per launch of the main kernels for a coil chunk cb,
+    split from the per-apply pass model: the six FFT passes read and write
+    their grids (x and the result once per apply); the gridding stage reads
+    the oversampled grid (interpolation, which also reads the 16-byte
+    trajectory and weight of every sample) and writes it (spreading).  The
+    sample values that pass from the interpolation to the spreading through
+    HBM are not algorithmic: a fused stage keeps them on chip."""
     nz, ny, nx, mz, my, mx, N = geom
     D, M = nz * ny * nx, mz * my * mx
     passes = 8 * (cb * (2 * D + 4 * mz * ny * nx + 4 * mz * my * nx + 2 * M) + 2 * D)
-    interp = 8 * M * cb + 16 * N + 8 * N * cb
-    spread = 8 * N * cb + 16 * N + 8 * M * cb
+    interp = 8 * M * cb + 16 * N
+    spread = 8 * M * cb
     return {"fft_pass": passes / 6.0, "interp": interp, "spread": spread}
 
 
