@@ -212,6 +212,21 @@ typedef struct {
                         sketches draw over them: V + S <= C0); 0 or >= C keeps
                         every coil.  Compressed maps [D][C0] and data [N][C0]
                         are allocated on first use */
+  int monitor;       /* SKETCH / SKETCH_LEARNED with l1-wavelet (no counterpart in
+                        the paper): non-zero evaluates the FP64 objective
+                        F(x) = 1/2 ||A x - y||^2 + lambda ||Psi x||_1 (Eqs. 3-4,
+                        as 1/2 <x, A^H A x> - Re <x, A^H y> + 1/2 ||y||^2 +
+                        lambda ||Psi x||_1 from the true gradient's apply) of
+                        x^{t0} and of every outer iterate.  An iterate whose F
+                        is not finite or exceeds F(x^t) + mon_tol |F(x^t)| is
+                        replaced by one full-coil proximal-gradient step from
+                        x^t, x^{t+1} = prox_{lambda / L}(x^t - d^t / L), with L
+                        from the power iteration on the full operator (run at
+                        the first fallback); the run then continues from it.
+                        Costs one more full-coil apply after the last outer
+                        iteration, two FP64 dot products and a wavelet
+                        transform per outer iteration */
+  double mon_tol;    /* the monitor's relative increase tolerance (>= 0) */
 } cs_recon_params;
 
 typedef struct {
@@ -235,6 +250,14 @@ typedef struct {
    * back to the plain start, and the GPU time of the warm-start decisions */
   long long n_warm_accepted, n_warm_rejected;
   double ms_warm;
+  /* monitor (cs_recon_params.monitor): host array of length >= T filled when
+   * non-NULL with F(x^{t0+it+1}) of the accepted iterate after outer
+   * iteration it; F(x^{t0}); the outer iterations replaced by the full-coil
+   * step; and the GPU time of the objective evaluations and fallbacks */
+  double* objective;
+  double objective0;
+  long long n_fallbacks;
+  double ms_monitor;
 } cs_recon_stats;
 
 /* Allocate recon_run's optional buffers now, so that recon_run allocates
@@ -266,7 +289,10 @@ int cs_reserve_recon(cs_ctx* ctx, int C0, int init_coils);
  * z0 = x^t + s_o CNN(x^t / s_x, d^t / s_d) (s_d = rms(d^t), s_o = alpha s_d,
  * s_x = rms(x^t) or s_o while x^t = 0) when the FP64 subproblem objective
  * at z0 is no larger than at x^t, else at x^t (the fallback); the
- * subproblems, hence the method's fixed point, are unchanged.  Synchronous. */
+ * subproblems, hence the method's fixed point, are unchanged.  The monitor
+ * (p->monitor) is for the l1-wavelet SKETCH and SKETCH_LEARNED modes only:
+ * CS_EINVAL with another mode or regularizer, or with mon_tol < 0 or NaN.
+ * Errors also: CS_ENUMERIC when the result holds NaN/Inf.  Synchronous. */
 int recon_run(cs_ctx* ctx, const void* y, const cs_recon_params* p,
               void* x_inout, cs_recon_stats* st);
 
@@ -299,8 +325,8 @@ int cs_cnn_train_step(cs_cnn* n, const float* in, const float* target, int nz, i
  * Algorithm 1 (mode CS_RECON_SKETCH parameters) from x_inout and writes, for
  * outer iteration t, the packed input at inputs + t D 4 and the target
  * (x^{t+1} - x^t) / s_o at targets + t D 2 (device FP32).  l1-wavelet on
- * all coils only: CS_EINVAL for another regularizer, for 0 < C0 < C and for
- * init_iters != 0.  Synchronous. */
+ * all coils only: CS_EINVAL for another regularizer, for 0 < C0 < C, for
+ * init_iters != 0 and for monitor != 0.  Synchronous. */
 int cs_cnn_collect(cs_ctx* ctx, const void* y, const cs_recon_params* p, void* x_inout,
                    float* inputs, float* targets);
 
@@ -336,7 +362,8 @@ const char* cs_batch_last_error(const cs_batch* b);
  * pointers), p[i] host params (mode CS_RECON_SKETCH, one T and K for all;
  * lam, V, S, seed, t0, step, n_pow per slice; x_ref and reuse_b ignored;
  * l1-wavelet on all coils: CS_EINVAL for another regularizer, for
- * 0 < C0 < C_i and for init_iters != 0), x[i] device [D_i] in/out.  use_graph = 0 issues the inner iterations
+ * 0 < C0 < C_i, for init_iters != 0 and for monitor != 0), x[i] device [D_i]
+ * in/out.  use_graph = 0 issues the inner iterations
  * eagerly (the reference for the graph path: same kernels, same results).
  * st: host array of n (may be NULL).  Synchronous: waits for earlier work on
  * the slice streams first and for all of its own work before returning. */

@@ -26,6 +26,12 @@ Readings:
     sketch drawn at t = 0 on both the model and the data and the same FISTA
     (step from the first subproblem) for a given number of iterations.
   * K inner FISTA iterations per subproblem.
+  * ``coil_sketch_monitored`` adds an objective monitor that the paper does
+    not have: F(x) = 1/2 ||A x - y||^2 + lambda ||Psi x||_1 (Eqs. 3-4) of
+    x^{t0} and of each outer iterate; an iterate whose F is not finite or
+    exceeds F(x^t) + tol |F(x^t)| is replaced by one proximal-gradient step
+    on the full problem from x^t with step 1/L, L from the power iteration
+    on the full normal operator, and the run continues from it.
 """
 from __future__ import annotations
 
@@ -170,3 +176,47 @@ def coil_sketch(normal_maps_fn, maps, y, dcf, b, x0, V, S, seed, T, K, lam,
         if callback is not None:
             callback(t, x)
     return x, alpha, st
+
+
+def fallback_step(x, d, L, lam, levels=4):
+    """The monitor's replacement iterate: one proximal-gradient step on the
+    full problem from x with gradient d, prox_{lam/L}(x - d/L)."""
+    return wv.prox_l1_wavelet(x - d / L, lam / L, levels)
+
+
+def coil_sketch_monitored(normal_maps_fn, forward_maps_fn, maps, y, dcf, b, x0, V, S, seed,
+                          T, K, lam, tol, alpha=None, levels=4, n_pow=30, t0=1,
+                          dist="rademacher"):
+    """Algorithm 1 (all coils, FISTA inner solves) with the objective monitor.
+
+    ``forward_maps_fn(x, maps)`` applies A (samples x coils, the layout of
+    ``y``).  Returns (x, alpha, F0, F, fell_back): F0 = F(x^{t0}), F[i] and
+    fell_back[i] those of the iterate kept after outer iteration i.
+    """
+    st = SketchState(maps, y, dcf)
+    if alpha is None:
+        m1 = st.maps_for(V, S, seed, t0, dist)
+        alpha = 1.0 / power_iteration(lambda v: normal_maps_fn(v, m1), x0.shape, n_pow)
+    full = lambda v: normal_maps_fn(v, maps)
+    F = lambda v: objective(v, lambda u: forward_maps_fn(u, maps), y, lam, levels)
+    x = np.array(x0, dtype=np.complex128, copy=True)
+    f_prev = F(x)
+    F0 = f_prev
+    L_full = None
+    objs, fell = [], []
+    for t in range(t0, t0 + T):
+        d = full(x) - b
+        mt = st.maps_for(V, S, seed, t, dist)
+        x_new = sketched_subproblem(lambda v: normal_maps_fn(v, mt), d, x, alpha, lam, K, levels)
+        with np.errstate(over="ignore", invalid="ignore"):
+            f = F(x_new)
+        bad = not np.isfinite(f) or f > f_prev + tol * abs(f_prev)
+        if bad:
+            if L_full is None:
+                L_full = power_iteration(full, x0.shape, n_pow)
+            x_new = fallback_step(x, d, L_full, lam, levels)
+            f = F(x_new)
+        objs.append(f)
+        fell.append(bad)
+        x, f_prev = x_new, f
+    return x, alpha, F0, objs, fell

@@ -86,6 +86,8 @@ class ReconParams(ctypes.Structure):
         ("n_cg", ctypes.c_int),
         ("init_iters", ctypes.c_int),
         ("C0", ctypes.c_int),
+        ("monitor", ctypes.c_int),
+        ("mon_tol", ctypes.c_double),
     ]
 
 
@@ -106,6 +108,10 @@ class ReconStats(ctypes.Structure):
         ("n_warm_accepted", ctypes.c_longlong),
         ("n_warm_rejected", ctypes.c_longlong),
         ("ms_warm", ctypes.c_double),
+        ("objective", ctypes.POINTER(ctypes.c_double)),
+        ("objective0", ctypes.c_double),
+        ("n_fallbacks", ctypes.c_longlong),
+        ("ms_monitor", ctypes.c_double),
     ]
 
 
@@ -229,6 +235,10 @@ class ReconResult:
     ms_warm: float = 0.0
     time_ms: list = field(default_factory=list)
     dist: list = field(default_factory=list)
+    objective0: float = 0.0
+    objective: list = field(default_factory=list)
+    n_fallbacks: int = 0
+    ms_monitor: float = 0.0
 
 
 def _geom(shape, ncoil, kind="cart", nsamp=0, sigma=1.25, kwidth=4, beta=0.0, wav_levels=4):
@@ -411,12 +421,15 @@ class Context:
 
     def recon_run(self, y, mode="sketch", lam=1e-3, T=10, K=5, V=2, S=2, seed=0, t0=1,
                   step=0.0, n_pow=30, reuse_b=False, x=None, x_ref=None, cnn=None,
-                  reg="l1wav", n_cg=5, init_iters=0, C0=0):
+                  reg="l1wav", n_cg=5, init_iters=0, C0=0, monitor=False, mon_tol=1e-4):
         """Algorithm 1 (mode "sketch", "learned") or the plain solver ("full")
         with regularizer reg: "l1wav" (FISTA), "l2" (conjugate gradients) or
         "tv" (PDHG with n_cg CG iterations per data-consistency step).
         init_iters > 0 runs the classical-sketch initialisation first; 0 < C0 < C
-        compresses to the first C0 virtual coils (Alg. 1's compression step)."""
+        compresses to the first C0 virtual coils (Alg. 1's compression step).
+        monitor=True evaluates the FP64 objective of every outer iterate and
+        replaces one that rose by more than mon_tol (relative) or is not
+        finite with a full-coil proximal-gradient step (l1wav Algorithm 1)."""
         self._data(y, self.C)
         if x is None:
             x = torch.zeros(self.shape, dtype=torch.complex64, device=self.device)
@@ -431,6 +444,8 @@ class Context:
         p.n_cg = int(n_cg)
         p.init_iters = int(init_iters)
         p.C0 = int(C0)
+        p.monitor = int(bool(monitor))
+        p.mon_tol = float(mon_tol)
         p.lam = float(lam)
         p.T, p.K, p.V, p.S = int(T), int(K), int(V), int(S)
         p.seed = int(seed)
@@ -442,9 +457,11 @@ class Context:
         n = max(1, int(T))
         dist = (ctypes.c_double * n)()
         tms = (ctypes.c_double * n)()
+        obj = (ctypes.c_double * n)()
         st = ReconStats()
         st.dist = ctypes.cast(dist, ctypes.POINTER(ctypes.c_double))
         st.time_ms = ctypes.cast(tms, ctypes.POINTER(ctypes.c_double))
+        st.objective = ctypes.cast(obj, ctypes.POINTER(ctypes.c_double))
         self._check(self.lib.recon_run(self._ctx, _ptr(y), ctypes.byref(p), _ptr(x),
                                        ctypes.byref(st)), "recon_run")
         return ReconResult(x=x, alpha=st.alpha, n_full_applies=st.n_full_applies,
@@ -455,7 +472,10 @@ class Context:
                            n_warm_accepted=st.n_warm_accepted,
                            n_warm_rejected=st.n_warm_rejected, ms_warm=st.ms_warm,
                            time_ms=list(tms[:T]),
-                           dist=list(dist[:T]) if x_ref is not None else [])
+                           dist=list(dist[:T]) if x_ref is not None else [],
+                           objective0=st.objective0,
+                           objective=list(obj[:T]) if monitor else [],
+                           n_fallbacks=st.n_fallbacks, ms_monitor=st.ms_monitor)
 
     def prox_l1wav(self, v, tau, out=None):
         self._img(v, "v")

@@ -1029,10 +1029,10 @@ int cs_cnn_collect(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_
   if (!y_ || !p || !x_inout || !inputs || !targets) return fail(c, CS_EINVAL, "null argument");
   if (p->T < 1 || p->K < 1) return fail(c, CS_EINVAL, "iteration counts");
   if (p->reg != CS_REG_L1WAV) return fail(c, CS_EINVAL, "pairs are collected for l1-wavelet only");
-  if ((p->C0 > 0 && p->C0 < c->C) || p->init_iters != 0)
+  if ((p->C0 > 0 && p->C0 < c->C) || p->init_iters != 0 || p->monitor != 0)
     return fail(c, CS_EINVAL,
-                "pairs are collected on all coils, without compression or the "
-                "classical-sketch initialisation");
+                "pairs are collected on all coils, without compression, the "
+                "classical-sketch initialisation or the objective monitor");
   const float2* y = (const float2*)y_;
   float2* x = (float2*)x_inout;
   const long long D = c->D;
@@ -1085,6 +1085,9 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
   if (p->init_iters < 0 ||
       (p->init_iters > 0 && (l2 || tvr || p->mode == CS_RECON_FULL)))
     return fail(c, CS_EINVAL, "the classical-sketch initialisation is for l1-wavelet Algorithm 1");
+  if (p->monitor && (l2 || tvr || p->mode == CS_RECON_FULL))
+    return fail(c, CS_EINVAL, "the objective monitor is for l1-wavelet Algorithm 1");
+  if (p->monitor && !(p->mon_tol >= 0.0)) return fail(c, CS_EINVAL, "mon_tol must be >= 0");
   if (p->C0 < 0) return fail(c, CS_EINVAL, "C0");
   if (p->C0 > 0 && p->C0 < c->C && p->init_iters > 0)
     return fail(c, CS_EINVAL, "the classical-sketch initialisation needs C0 = C");
@@ -1092,7 +1095,12 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
     return fail(c, CS_EINVAL, "sketch sizes: need V + S <= C0");
   if (p->T < 0 || (p->mode != CS_RECON_FULL && p->K < 1))
     return fail(c, CS_EINVAL, "iteration counts");
-  if (st) st->n_warm_accepted = st->n_warm_rejected = 0;
+  if (st) {
+    st->n_warm_accepted = st->n_warm_rejected = 0;
+    st->n_fallbacks = 0;
+    st->objective0 = 0.0;
+    st->ms_monitor = 0.0;
+  }
   const float2* y = (const float2*)y_;
   float2* x = (float2*)x_inout;
   const long long D = c->D;
@@ -1448,12 +1456,80 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
       }
       return CS_OK;
     };
+    // objective monitor (no counterpart in the paper): with g = A^H A x from
+    // the true gradient's apply,
+    //   F(x) = 1/2 <x, g> - Re<x, b> + 1/2 ||y||^2 + lam ||Psi x||_1
+    // (= 1/2 ||A x - y||^2 + lam ||Psi x||_1, Eqs. 3-4).  The iterate left by
+    // an outer iteration is replaced, when its F is not finite or rose by
+    // more than mon_tol |F(x^t)|, by the full-coil proximal-gradient step
+    // x^t - d^t / L, prox_{lam / L}, whose step 1/L (L of the full operator)
+    // cannot raise F
+    const bool mon = p->monitor != 0;
+    float2* xprev = c->img[10];
+    float2* dprev = c->img[11];
+    double yy = 0.0, fprev = 0.0, f0 = 0.0, af = 0.0;
+    long long n_fb = 0;
+    std::vector<double> fobj;
+    if (mon && c->N > 0) {
+      const float2* ydata = compress ? c->ycmp : y;
+      double o[2];
+      CS_TRY(timed(5, [&] { return vec_dot(c, ydata, ydata, c->N * FC, o); }));
+      yy = o[0];
+    }
+    auto objective = [&](double* f) -> int {
+      double xg[2], xb[2], l1 = 0.0;
+      CS_TRY(vec_dot(c, x, g, D, xg));
+      CS_TRY(vec_dot(c, x, b, D, xb));
+      CS_TRY(dwt_fwd(c, x, v));
+      CS_TRY(vec_abs_sum(c, v, D, &l1));
+      *f = 0.5 * xg[0] - xb[0] + 0.5 * yy + p->lam * l1;
+      return CS_OK;
+    };
+    // x, g and d hold the iterate left by outer iteration it and its gradient
+    // pair; xprev, dprev those of the iterate it started from
+    auto monitor = [&](int it) -> int {
+      double f = 0.0;
+      CS_TRY(timed(5, [&] { return objective(&f); }));
+      if (!std::isfinite(f) || f > fprev + p->mon_tol * std::fabs(fprev)) {
+        if (af <= 0.0) {
+          double L = 0.0;
+          CS_TRY(timed(0, [&] { return power_iter(c, fmaps, FC, n_pow, &L); }));
+          nfull += n_pow + 1;
+          af = 1.0 / L;
+        }
+        CS_TRY(timed(5, [&] {
+          CS_TRY(vec_fista_step(c, v, xprev, (float)af, dprev, 0.f, dprev, D));
+          return prox_l1(c, v, (float)(af * p->lam), x);
+        }));
+        ++nprox;
+        CS_TRY(timed(0, [&] { return op_normal(c, fmaps, FC, x, g); }));
+        ++nfull;
+        CS_TRY(vec_axpby(c, d, 1.f, g, -1.f, b, D));
+        CS_TRY(timed(5, [&] { return objective(&f); }));
+        ++n_fb;
+        if (track)
+          CS_TRY(vec_dist(c, x, (const float2*)p->x_ref, D, &dist_num[it], &dist_den[it]));
+      }
+      fobj.push_back(f);
+      fprev = f;
+      return CS_OK;
+    };
     for (int it = 0; it < p->T; ++it) {
       const int t = p->t0 + it;
       // true gradient d = A^H (A x^t - y) = A^H A x^t - b (Alg. 1, true gradient)
       CS_TRY(timed(0, [&] { return op_normal(c, fmaps, FC, x, g); }));
       ++nfull;
       CS_TRY(vec_axpby(c, d, 1.f, g, -1.f, b, D));
+      if (mon) {
+        if (it == 0) {
+          CS_TRY(timed(5, [&] { return objective(&fprev); }));
+          f0 = fprev;
+        } else {
+          CS_TRY(monitor(it - 1));
+        }
+        CS_TRY(vec_copy(c, xprev, x, D));
+        CS_TRY(vec_copy(c, dprev, d, D));
+      }
       // sketched model A_S^t (Alg. 1, per-iteration sketch)
       if (it > 0)
         CS_TRY(timed(3, [&] {
@@ -1467,9 +1543,20 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
       nprox += p->K;
       CS_TRY(record(it));
     }
+    if (mon && p->T > 0) {
+      // the last iterate's gradient, for its objective
+      CS_TRY(timed(0, [&] { return op_normal(c, fmaps, FC, x, g); }));
+      ++nfull;
+      CS_TRY(vec_axpby(c, d, 1.f, g, -1.f, b, D));
+      CS_TRY(monitor(p->T - 1));
+    }
     if (st) {
       st->n_warm_accepted = n_acc;
       st->n_warm_rejected = n_rej;
+      st->n_fallbacks = n_fb;
+      st->objective0 = f0;
+      if (st->objective)
+        for (size_t k = 0; k < fobj.size(); ++k) st->objective[k] = fobj[k];
     }
   }
   CS_HIP(c, hipEventRecord(ev_end, c->stream));
@@ -1494,7 +1581,7 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
     st->n_prox = nprox;
     st->total_ms = total - excluded;
     st->prep_ms = prep;
-    double pms[5] = {0, 0, 0, 0, 0};
+    double pms[6] = {0, 0, 0, 0, 0, 0};
     for (auto& ph : phases) {
       float ms = 0.f;
       CS_HIP(c, hipEventElapsedTime(&ms, ph.a, ph.b));
@@ -1505,6 +1592,7 @@ int recon_run(cs_ctx* c, const void* y_, const cs_recon_params* p, void* x_inout
     st->ms_prox = pms[2];
     st->ms_sketch = pms[3];
     st->ms_warm = pms[4];
+    st->ms_monitor = pms[5];
   }
   double chk[2];
   CS_TRY(vec_dot(c, x, x, D, chk));

@@ -139,10 +139,10 @@ int cs_batch_recon(cs_batch* b, const void* const* y, const cs_recon_params* p,
     if (p[i].mode != CS_RECON_SKETCH || p[i].reg != CS_REG_L1WAV || p[i].T != T ||
         p[i].K != K || K < 1 || T < 0)
       return bfail(b, CS_EINVAL, "every slice needs SKETCH mode and the same T and K");
-    if ((p[i].C0 > 0 && p[i].C0 < c->C) || p[i].init_iters != 0)
+    if ((p[i].C0 > 0 && p[i].C0 < c->C) || p[i].init_iters != 0 || p[i].monitor != 0)
       return bfail(b, CS_EINVAL,
-                   "the batch runs Algorithm 1 on all coils, without compression or the "
-                   "classical-sketch initialisation");
+                   "the batch runs Algorithm 1 on all coils, without compression, the "
+                   "classical-sketch initialisation or the objective monitor");
   }
   drop_graph(b);
   for (auto* c : b->ctx) CS_BHIP(b, hipStreamSynchronize(c->stream));

@@ -78,3 +78,54 @@ def test_recon_cones_48():
     e = orecon.nrmse(h(res.x), xr)
     assert e < 1e-3, e
     ctx.close()
+
+
+def test_recon_monitor_cartesian():
+    # objective monitor: F(x^t) against the oracle's F of its own iterates
+    # (relative 1e-3), no fallback and no change to x on a converging run;
+    # with the inner step forced 30x too large from the host every outer
+    # iterate is replaced by the full-coil proximal-gradient step, matching
+    # the oracle's monitored run (NRMSE <= 1e-3) with a non-increasing F
+    dev()
+    import torch
+    from paper_2305_06482_amd import CSError, Context
+    p = synth.make_cart_small()
+    case("recon monitor cart128")
+    y, maps = _cart_problem(p)
+    C = p.n_coils
+    yr = y.reshape(-1, C)
+    nf = lambda v, m: cart.normal(v, m, p.mask)
+    fwd = lambda v, m: cart.forward(v, m, p.mask).reshape(-1, m.shape[-1])
+    b = cart.adjoint(y, maps, p.mask)
+    T, K = 4, 5
+    x0 = np.zeros(p.shape, complex)
+    _, alpha, _ = orecon.coil_sketch(nf, maps, yr, None, b, x0, p.V, p.S, p.seed, 0, K, p.lam)
+    ctx = Context(p.shape, C, "cart")
+    ctx.set_operator(t(maps), mask=t(p.mask, torch.uint8))
+    yt = t(y)
+    kw = dict(mode="sketch", lam=p.lam, T=T, K=K, V=p.V, S=p.S, seed=p.seed)
+    plain = ctx.recon_run(yt, step=alpha, **kw)
+    for scale, fallbacks in ((1.0, 0), (30.0, T)):
+        case(f"recon monitor cart128 step x{scale}")
+        xm, _, F0, F, fell = orecon.coil_sketch_monitored(
+            nf, fwd, maps, yr, None, b, x0, p.V, p.S, p.seed, T, K, p.lam, 0.0,
+            alpha=scale * alpha)
+        assert sum(fell) == fallbacks
+        res = ctx.recon_run(yt, step=scale * alpha, monitor=True, mon_tol=0.0, reuse_b=True, **kw)
+        assert res.n_fallbacks == fallbacks
+        assert res.n_full_applies == T + 1 + (fallbacks + 31 if fallbacks else 0)
+        assert abs(res.objective0 - F0) <= 1e-6 * F0
+        for got, want in zip(res.objective, F):
+            assert abs(got - want) <= 1e-3 * want, (got, want)
+        e = orecon.nrmse(h(res.x), xm)
+        assert e < 1e-3, e
+        if fallbacks == 0:
+            assert torch.equal(res.x, plain.x)
+        else:
+            seq = [res.objective0] + res.objective
+            assert all(seq[i + 1] <= seq[i] * (1 + 1e-5) for i in range(T)), seq
+    with pytest.raises(CSError, match="monitor"):
+        ctx.recon_run(yt, mode="full", lam=p.lam, T=2, step=alpha, monitor=True)
+    with pytest.raises(CSError, match="mon_tol"):
+        ctx.recon_run(yt, step=alpha, monitor=True, mon_tol=-1.0, **kw)
+    ctx.close()

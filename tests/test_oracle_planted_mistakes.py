@@ -276,6 +276,14 @@ def nrmse_over_x(x, ref):
     return float(np.linalg.norm((x - ref).ravel()) / np.linalg.norm(x.ravel()))
 
 
+def fallback_step_ascending(x, d, L, lam, levels=4):
+    return wavelet.prox_l1_wavelet(x + d / L, lam / L, levels)
+
+
+def fallback_step_half_threshold(x, d, L, lam, levels=4):
+    return wavelet.prox_l1_wavelet(x - d / L, 0.5 * lam / L, levels)
+
+
 CASES = [
     # (name, owner, attribute, planted function, pins expected to fail)
     ("cartesian forward drops the mask", cartesian, "forward", cart_forward_without_mask,
@@ -349,6 +357,10 @@ CASES = [
      [p_recon.test_objective_of_wavelet_atoms_closed_form]),
     ("NRMSE of squared norms", recon, "nrmse", nrmse_squared, [p_recon.test_nrmse_hand_computed]),
     ("NRMSE normalised by x", recon, "nrmse", nrmse_over_x, [p_recon.test_nrmse_hand_computed]),
+    ("monitor fallback along +d", recon, "fallback_step", fallback_step_ascending,
+     [p_recon.test_monitor_with_a_diverging_inner_step_is_ista]),
+    ("monitor fallback with half the threshold", recon, "fallback_step",
+     fallback_step_half_threshold, [p_recon.test_monitor_with_a_diverging_inner_step_is_ista]),
 ]
 
 

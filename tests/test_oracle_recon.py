@@ -1,12 +1,14 @@
 """Pins for the solvers: IHS closed form with lambda = 0, V = C reduction to
-plain FISTA, the fixed point of an outer iteration, and the power iteration
-against the full-mask closed form."""
+plain FISTA, the fixed point of an outer iteration, the power iteration
+against the full-mask closed form, and the objective monitor's reductions
+(never firing: Algorithm 1; always firing: ISTA with a monotone objective)."""
 import numpy as np
 
 import synth
 from oracle import cartesian as cart
 from oracle import recon
 from oracle import sketch as sk
+from oracle import wavelet as wv
 
 
 def _rand(shape, seed):
@@ -295,3 +297,60 @@ def test_nrmse_hand_computed():
     # arrays of any shape are flattened: ||(3, 0, 0, 4)|| / ||(0, 0, 0, 2)|| = 5 / 2
     assert math.isclose(recon.nrmse(np.array([[3.0, 0.0], [0.0, 6.0]]),
                                     np.array([[0.0, 0.0], [0.0, 2.0]])), 2.5, rel_tol=1e-15)
+
+
+def _monitored(seed, tol, alpha_scale, T=4, K=5, lam=1e-3, V=2, S=2):
+    shape, x, maps, mask, y = _small(seed=seed, C=6)
+    C = maps.shape[-1]
+    nf = _nfn(mask)
+    fwd = lambda v, m: cart.forward(v, m, mask).reshape(-1, m.shape[-1])
+    b = cart.adjoint(y.reshape(shape + (C,)), maps, mask)
+    st = recon.SketchState(maps, y, None)
+    Ls = recon.power_iteration(lambda v: nf(v, st.maps_for(V, S, 7, 1)), shape)
+    alpha = alpha_scale / Ls
+    out = recon.coil_sketch_monitored(nf, fwd, maps, y, None, b, np.zeros(shape, complex),
+                                      V, S, 7, T, K, lam, tol, alpha=alpha)
+    return shape, maps, mask, y, b, alpha, out
+
+
+def test_monitor_that_never_fires_is_algorithm1():
+    # an infinite tolerance never replaces an iterate: the monitored run is
+    # Algorithm 1 itself
+    shape, maps, mask, y, b, alpha, (xm, _, F0, F, fell) = _monitored(50, np.inf, 1.0)
+    xr, _, _ = recon.coil_sketch(_nfn(mask), maps, y, None, b, np.zeros(shape, complex),
+                                 2, 2, 7, 4, 5, 1e-3, alpha=alpha)
+    assert not any(fell)
+    assert np.array_equal(xm, xr)
+    # the objective of x^0 = 0 is 1/2 ||y||^2
+    assert abs(F0 - 0.5 * np.vdot(y, y).real) <= 1e-12 * F0
+
+
+def test_monitor_with_a_diverging_inner_step_is_ista():
+    # a sketched step of 30/L_S makes every subproblem's FISTA diverge, so each
+    # outer iterate is replaced: the run is then proximal-gradient descent
+    # (ISTA) on the full problem with step 1/L, whose objective cannot rise
+    # (Beck & Teboulle 2009, Lemma 2.3)
+    shape, maps, mask, y, b, alpha, (xm, _, F0, F, fell) = _monitored(51, 0.0, 30.0, T=5)
+    assert all(fell)
+    nf = lambda v: cart.normal(v, maps, mask)
+    L = recon.power_iteration(nf, shape)
+    x = np.zeros(shape, complex)
+    for _ in range(5):
+        x = wv.prox_l1_wavelet(x - (nf(x) - b) / L, 1e-3 / L, 4)
+    assert np.allclose(xm, x, rtol=0, atol=1e-12 * np.abs(x).max())
+    seq = [F0] + F
+    assert all(seq[i + 1] <= seq[i] * (1 + 1e-12) for i in range(len(seq) - 1))
+
+
+def test_monitor_objective_expansion_matches_definition():
+    # the monitor's objective expanded through the normal operator,
+    # 1/2 <x, N x> - Re <x, A^H y> + 1/2 ||y||^2, equals 1/2 ||A x - y||^2
+    shape, x, maps, mask, y = _small(seed=52, C=6)
+    C = maps.shape[-1]
+    v = _rand(shape, 53)
+    r = cart.forward(v, maps, mask).reshape(-1, C) - y
+    direct = 0.5 * np.vdot(r, r).real
+    b = cart.adjoint(y.reshape(shape + (C,)), maps, mask)
+    expanded = (0.5 * np.vdot(v, cart.normal(v, maps, mask)).real - np.vdot(v, b).real
+                + 0.5 * np.vdot(y, y).real)
+    assert abs(direct - expanded) <= 1e-10 * direct
