@@ -57,6 +57,9 @@ struct PassArgs {
   const float* da;       // [n] per-row scale along the pass axis
   const float* dp;       // [P] per-pixel scale of the other axes
   int xcd;               // 1: each XCD takes a contiguous range of panels
+  // 1: the panel is loaded (stored) as pairs of adjacent columns, 16 bytes
+  // per thread and row (grid source / destination with contiguous columns)
+  int vec_in, vec_out;
 };
 
 // Work-groups are dealt to the 8 XCDs in turn (group b to XCD b mod 8), and
@@ -115,7 +118,9 @@ struct cs_ctx {
   std::map<int, cs::FFTPlan> plans;
   // FFT pass panels: pixels per panel of an image pass (all coils of each)
   // and columns per panel of a grid pass (CS_FFT_PIX / CS_FFT_COLS)
-  int fft_pix = 1, fft_cols = 12;
+  int fft_pix = 1, fft_cols = 16;
+  int fft_vec = 1;  // paired-column loads and stores in the grid passes
+  int grid_vec = 1;  // paired-coil accesses in the interpolation and merge
   int fft_xcd = 1;                // XCD-contiguous panel order in the FFT passes
   int grid_xcd = 1;               // gridding: an item's coil groups on one XCD
   int merge_xcd = 0;              // merge: each XCD a contiguous range of tiles

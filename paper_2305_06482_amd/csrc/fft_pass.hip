@@ -344,7 +344,30 @@ __global__ __launch_bounds__(256) void k_pass_t(PassArgs a) {
   // rows t = tr + i TR, i < NR: a thread's rows are loaded in one unrolled
   // sweep (every load issued before the first wait) and then stored to LDS
   constexpr int NR = (L + TR - 1) / TR;
-  if (colok) {
+  // paired columns: thread (rv, tp) moves columns 2 tp, 2 tp + 1 of rows
+  // rv + i RV as one 16-byte access
+  constexpr int TP = TC / 2, RV = NT / TP, NRV = (L + RV - 1) / RV;
+  static_assert(TC % 2 == 0 && NT % TP == 0, "column pairs");
+  if (a.vec_in) {
+    const int tp = tid % TP, rv = tid / TP;
+    if (2 * tp < ncol) {
+      const float4* s4 = reinterpret_cast<const float4*>(a.src + outer * a.src_os + col0) + tp;
+      const long long rs4 = a.src_rs / 2;
+      float4 w[NRV];
+#pragma unroll
+      for (int i = 0; i < NRV; ++i) {
+        const int t = rv + i * RV;
+        w[i] = t < a.n_in ? s4[(long long)t * rs4] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int i = 0; i < NRV; ++i) {
+        const int t = rv + i * RV;
+        if (t < a.n_in)
+          *reinterpret_cast<float4*>(buf + (a.pad_in ? wrap_row(t, a.n_in, L) : t) * TC +
+                                     2 * tp) = w[i];
+      }
+    }
+  } else if (colok) {
     const uint8_t* mrow = a.premask ? a.mask + outer * a.mask_os : nullptr;
     float2 v[NR];
     if (a.prologue == PRO_IMAGE) {
@@ -440,6 +463,16 @@ __global__ __launch_bounds__(256) void k_pass_t(PassArgs a) {
           if (a.accumulate) acc = cadd(acc, prev[i]);
           a.img_out[(long long)t * a.P + p] = acc;
         }
+      }
+    }
+  } else if (a.vec_out) {
+    const int tp = tid % TP, rv = tid / TP;
+    if (2 * tp < ncol) {
+      float4* d4 = reinterpret_cast<float4*>(a.dst + outer * a.dst_os + col0) + tp;
+      const long long rs4 = a.dst_rs / 2;
+      for (int t = rv; t < a.n_out; t += RV) {
+        const int row = a.pad_out ? wrap_row(t, a.n_out, L) : t;
+        d4[(long long)t * rs4] = *reinterpret_cast<const float4*>(buf + row * TC + 2 * tp);
       }
     }
   } else if (colok) {
@@ -568,6 +601,15 @@ int launch_pass(cs_ctx* c, PassArgs& a, long long n_outer) {
     if (fits(TC)) {
       a.xcd = c->fft_xcd;
       a.Wt = (int)w;
+      // column pairs: contiguous columns (ldc = cb, c0 = 0), every row and
+      // panel start on an even column and 16-byte aligned pointers
+      const bool even = a.Wt % 2 == 0 && a.inner % 2 == 0;
+      a.vec_in = c->fft_vec && even && a.prologue == PRO_GRID && !a.premask &&
+                 a.src_ldc == a.cb && a.src_c0 == 0 && a.src_os % 2 == 0 &&
+                 a.src_rs % 2 == 0 && ((uintptr_t)a.src & 15) == 0;
+      a.vec_out = c->fft_vec && even && a.epilogue != EPI_IMAGE && a.dst_ldc == a.cb &&
+                  a.dst_c0 == 0 && a.dst_os % 2 == 0 && a.dst_rs % 2 == 0 &&
+                  ((uintptr_t)a.dst & 15) == 0;
       const long long nblk = (a.inner + a.Wt - 1) / a.Wt;
       a.nblk = nblk;
       if (nblk * n_outer > 0x7fffffffLL || n_outer < 1)

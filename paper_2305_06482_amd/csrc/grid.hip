@@ -135,13 +135,15 @@ inline dim3 item_group_grid(long long nitems, int ng, int xcd) {
 // 4^d taps in the order z, y, x with weight (wz wy) wx, so both variants give
 // the same values.  The sum is scaled by w (W_FULL), sqrt(w) (W_SQRT) or 1,
 // and written to row `voff + k - kbeg` of `out` (values of the item group)
-// or, with caller_order, to row orig[k] (the caller's sample order).
+// or, with caller_order, to row orig[k] (the caller's sample order).  With
+// vec (even cb, ldc and c0, 16-byte aligned G and out), a full group moves
+// its coils two at a time, 16 bytes per access.
 template <int NDIM, int CG, int NT, bool TILE, bool IL = false>
 __global__ __launch_bounds__(NT) void k_interp_items(
     const float2* __restrict__ G, int mx, int my, int mz, int cb,
     const SampleRec* __restrict__ rec, const GridItem* __restrict__ items, int item0,
     int ntx, int nty, int wmode, float2* __restrict__ out, int ldc, int c0,
-    int caller_order, int nitems, int xcd) {
+    int caller_order, int nitems, int xcd, int vec) {
   using H = Halo<NDIM>;
   extern __shared__ float lds[];  // [CG][2][PLANE]
   int item, grp;
@@ -149,6 +151,7 @@ __global__ __launch_bounds__(NT) void k_interp_items(
   const GridItem it = items[item0 + item];
   const int tile = it.tile, kbeg = it.kbeg, kend = it.kend;
   const int cg0 = grp * CG, cga = min(CG, cb - cg0);
+  const bool v2 = CG % 2 == 0 && vec && cga == CG;
   const int ix = tile % ntx, iy = (tile / ntx) % nty, iz = tile / (ntx * nty);
   const int x0 = ix * H::TX, y0 = iy * H::TY, z0 = iz * H::TZ;
   const int tid = threadIdx.x;
@@ -181,8 +184,17 @@ __global__ __launch_bounds__(NT) void k_interp_items(
         }
         const float2* src = G + (((long long)gz * my + gy) * mx + gx) * cb + cg0;
         ta[i] = lz * H::PZ + ly * H::PY + lx;
+        if (v2) {
 #pragma unroll
-        for (int q = 0; q < CG; ++q) tv[i][q] = q < cga ? src[q] : make_float2(0.f, 0.f);
+          for (int q = 0; q < CG / 2; ++q) {
+            const float4 t = reinterpret_cast<const float4*>(src)[q];
+            tv[i][2 * q] = make_float2(t.x, t.y);
+            tv[i][2 * q + 1] = make_float2(t.z, t.w);
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < CG; ++q) tv[i][q] = q < cga ? src[q] : make_float2(0.f, 0.f);
+        }
       }
     }
 #pragma unroll
@@ -268,9 +280,17 @@ __global__ __launch_bounds__(NT) void k_interp_items(
     const float s = wmode == W_FULL ? r.w : (wmode == W_SQRT ? r.sw : 1.f);
     const long long o = caller_order ? (long long)r.orig : (long long)(it.voff + k - kbeg);
     float2* dst = out + o * ldc + c0 + cg0;
+    if (v2) {
 #pragma unroll
-    for (int q = 0; q < CG; ++q)
-      if (q < cga) dst[q] = make_float2(acc[q].x * s, acc[q].y * s);
+      for (int q = 0; q < CG / 2; ++q)
+        reinterpret_cast<float4*>(dst)[q] = make_float4(acc[2 * q].x * s, acc[2 * q].y * s,
+                                                        acc[2 * q + 1].x * s,
+                                                        acc[2 * q + 1].y * s);
+    } else {
+#pragma unroll
+      for (int q = 0; q < CG; ++q)
+        if (q < cga) dst[q] = make_float2(acc[q].x * s, acc[q].y * s);
+    }
   }
 }
 
@@ -293,9 +313,11 @@ int interp_launch(cs_ctx* c, const float2* grid, int cb, int item0, int nitems, 
   if (lds > 64 * 1024)
     CS_HIP(c, hipFuncSetAttribute((const void*)kern,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  const int vec = c->grid_vec && cb % 2 == 0 && ldc % 2 == 0 && c0 % 2 == 0 &&
+                  ((uintptr_t)grid & 15) == 0 && ((uintptr_t)out & 15) == 0;
   CS_KLAUNCH(c, K_INTERP, kern, item_group_grid(nitems, ng, c->grid_xcd), dim3(NT), lds,
              c->stream, grid, c->mx, c->my, c->mz, cb, c->rec, c->gitems, item0, c->ntile[2],
-             c->ntile[1], wmode, out, ldc, c0, caller_order, nitems, c->grid_xcd);
+             c->ntile[1], wmode, out, ldc, c0, caller_order, nitems, c->grid_xcd, vec);
   CS_HIP(c, hipGetLastError());
   return CS_OK;
 }
@@ -937,7 +959,7 @@ __device__ __forceinline__ int halo_cover(int g, int ig, int nt, int T, int m, i
 template <int NDIM, int CG>
 __global__ __launch_bounds__(256) void k_spread_merge(
     const float2* __restrict__ P, const int* __restrict__ item_off, int cb, int ng, int ntx,
-    int nty, int ntz, int mx, int my, int mz, float2* __restrict__ G, int xcd) {
+    int nty, int ntz, int mx, int my, int mz, float2* __restrict__ G, int xcd, int vec) {
   using H = Halo<NDIM>;
   constexpr int TV = H::TX * H::TY * H::TZ;
   constexpr int BPT = (TV + 255) / 256;  // blocks per tile
@@ -983,9 +1005,18 @@ __global__ __launch_bounds__(256) void k_spread_merge(
         }
       }
   float2* out = G + (((long long)gz * my + gy) * mx + gx) * cb;
+  if (vec) {
+    // even cb, 16-byte aligned G: coils two at a time
 #pragma unroll
-  for (int c = 0; c < NGMAX * CG; ++c)
-    if (c < cb) out[c] = acc[c];
+    for (int c = 0; c + 1 < NGMAX * CG; c += 2)
+      if (c < cb)
+        reinterpret_cast<float4*>(out)[c / 2] =
+            make_float4(acc[c].x, acc[c].y, acc[c + 1].x, acc[c + 1].y);
+  } else {
+#pragma unroll
+    for (int c = 0; c < NGMAX * CG; ++c)
+      if (c < cb) out[c] = acc[c];
+  }
 }
 
 template <int NDIM, int NW, int CW>
@@ -1041,9 +1072,11 @@ int merge_launch(cs_ctx* c, int cb, float2* grid) {
   constexpr long long TV = (long long)H::TX * H::TY * H::TZ;
   const long long blocks = c->ntiles * ((TV + 255) / 256);
   if (blocks > 0x7fffffffLL) return fail(c, CS_EINVAL, "spread merge grid too large");
+  constexpr int NA = ((kCoilChunk + CG - 1) / CG) * CG;
+  const int vec = c->grid_vec && cb % 2 == 0 && NA % 2 == 0 && ((uintptr_t)grid & 15) == 0;
   CS_KLAUNCH(c, K_MERGE, (k_spread_merge<NDIM, CG>), dim3((unsigned)blocks), dim3(256), 0,
              c->stream, c->partial, c->item_off, cb, ng, c->ntile[2], c->ntile[1],
-             c->ntile[0], c->mx, c->my, c->mz, grid, c->merge_xcd);
+             c->ntile[0], c->mx, c->my, c->mz, grid, c->merge_xcd, vec);
   CS_HIP(c, hipGetLastError());
   return CS_OK;
 }
