@@ -130,3 +130,53 @@ def test_interp_variants_agree(kind, C):
         for a, b in zip(out[0], out[v]):
             assert rel(b, a) < 1e-6
     ctx.close()
+
+
+@pytest.mark.parametrize("kind,C", [("radial", 12), ("cones", 12), ("cones", 16), ("cones", 32),
+                                    ("cones", 5), ("cart", 8)])
+def test_paired_accesses_are_bit_identical(kind, C, monkeypatch):
+    """The 16-byte coil-pair accesses of the grid FFT passes, the
+    interpolation and the merge (the default) against one coil per access
+    (CS_FFT_VEC=0 and CS_GRID_VEC=0 when the context is made): the same
+    values move in the same order, so the forward, adjoint and normal
+    applies agree bit for bit (odd coil counts take the one-coil path
+    either way)."""
+    dev()
+    import torch
+    from paper_2305_06482_amd import Context
+    case(f"paired accesses {kind} C={C}")
+    if kind == "radial":
+        shape = (40, 40)
+        coords = synth.radial_traj(40, 21)
+        dcf = synth.radial_dcf(coords, 40)
+    elif kind == "cones":
+        shape = (16, 24, 24)
+        coords = synth.cones_traj(shape, 140, 40, seed=5)
+        dcf = synth.cones_dcf(coords, shape)
+    else:
+        shape = (48, 40)
+        mask = synth.mask_1d_vd(48, 40, 3, n_center=8, accel=2)
+    maps = synth.coil_maps(shape, C, 7)
+    x = synth.phantom(shape, 2) + 0.1 * rng_c(shape, 11)
+    mt, xt = t(maps), t(x)
+    outs = []
+    for env in ({}, {"CS_FFT_VEC": "0", "CS_GRID_VEC": "0"}):
+        for k in ("CS_FFT_VEC", "CS_GRID_VEC"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        if kind == "cart":
+            ctx = Context(shape, C, "cart", wav_levels=2)
+            ctx.set_operator(mt, mask=t(mask, torch.uint8))
+            yshape = shape + (C,)
+        else:
+            ctx = Context(shape, C, "noncart", nsamp=coords.shape[0], sigma=1.25, wav_levels=2)
+            ctx.set_operator(mt, coords=t(coords.astype(np.float32)),
+                             dcf=t(dcf.astype(np.float32)))
+            yshape = (coords.shape[0], C)
+        yt = t(rng_c(yshape, 4))
+        outs.append((h(ctx.sense_apply(mt, xt)), h(ctx.sense_adjoint(mt, yt)),
+                     h(ctx.normal_apply(mt, xt))))
+        ctx.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
