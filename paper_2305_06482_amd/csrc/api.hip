@@ -475,6 +475,8 @@ int create_impl(const cs_geom* g, void* workspace, size_t ws_bytes, void* stream
   if (const char* e = std::getenv("CS_FFT_PIX")) c->fft_pix = std::max(1, std::atoi(e));
   if (const char* e = std::getenv("CS_FFT_COLS")) c->fft_cols = std::max(1, std::atoi(e));
   if (const char* e = std::getenv("CS_FFT_VEC")) c->fft_vec = std::atoi(e) != 0;
+  if (const char* e = std::getenv("CS_FFT_PRO_COLS")) c->fft_pro_cols = std::atoi(e);
+  if (const char* e = std::getenv("CS_FFT_VEC_IMG")) c->fft_vec_img = std::atoi(e) != 0;
   if (const char* e = std::getenv("CS_GRID_VEC")) c->grid_vec = std::atoi(e) != 0;
   if (const char* e = std::getenv("CS_FFT_XCD")) c->fft_xcd = std::atoi(e) != 0;
   auto reqs = ws_requests(c);

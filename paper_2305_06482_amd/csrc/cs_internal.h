@@ -60,6 +60,7 @@ struct PassArgs {
   // 1: the panel is loaded (stored) as pairs of adjacent columns, 16 bytes
   // per thread and row (grid source / destination with contiguous columns)
   int vec_in, vec_out;
+  int vec_img;  // the image prologue on coil pairs of one pixel
 };
 
 // Work-groups are dealt to the 8 XCDs in turn (group b to XCD b mod 8), and
@@ -119,6 +120,8 @@ struct cs_ctx {
   // FFT pass panels: pixels per panel of an image pass (all coils of each)
   // and columns per panel of a grid pass (CS_FFT_PIX / CS_FFT_COLS)
   int fft_pix = 1, fft_cols = 16;
+  int fft_pro_cols = 16;  // > 0: image-prologue passes in panels of this many columns
+  int fft_vec_img = 1;    // image prologue loads maps as coil pairs
   int fft_vec = 1;  // paired-column loads and stores in the grid passes
   int grid_vec = 1;  // paired-coil accesses in the interpolation and merge
   int fft_xcd = 1;                // XCD-contiguous panel order in the FFT passes

@@ -367,6 +367,39 @@ __global__ __launch_bounds__(256) void k_pass_t(PassArgs a) {
                                      2 * tp) = w[i];
       }
     }
+  } else if (a.vec_img) {
+    // image prologue on column pairs: both columns are coils of one pixel
+    // (even cb), whose map values are adjacent
+    const int tp = tid % TP, rv = tid / TP;
+    if (2 * tp < ncol) {
+      const long long ci2 = col0 + 2 * tp;
+      const long long pp = ci2 / a.cb;
+      const int cc = (int)(ci2 - pp * a.cb);
+      const float dpv = a.dp[pp];
+      float4 w[NRV];
+#pragma unroll
+      for (int i = 0; i < NRV; ++i) {
+        const int t = rv + i * RV;
+        w[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (t < a.n_in) {
+          const long long pix = (long long)t * a.P + pp;
+          const float2 xv = a.img[pix];
+          const float4 m =
+              *reinterpret_cast<const float4*>(a.maps + pix * a.maps_ldc + a.maps_c0 + cc);
+          const float sc = a.da[t] * dpv;
+          const float2 v0 = cscale(cmul(xv, make_float2(m.x, m.y)), sc);
+          const float2 v1 = cscale(cmul(xv, make_float2(m.z, m.w)), sc);
+          w[i] = make_float4(v0.x, v0.y, v1.x, v1.y);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NRV; ++i) {
+        const int t = rv + i * RV;
+        if (t < a.n_in)
+          *reinterpret_cast<float4*>(buf + (a.pad_in ? wrap_row(t, a.n_in, L) : t) * TC +
+                                     2 * tp) = w[i];
+      }
+    }
   } else if (colok) {
     const uint8_t* mrow = a.premask ? a.mask + outer * a.mask_os : nullptr;
     float2 v[NR];
@@ -587,15 +620,20 @@ int launch_pass(cs_ctx* c, PassArgs& a, long long n_outer) {
     // coils of each), grid passes c->fft_cols columns; the column group is
     // the narrowest kernel width that holds the panel, kept to at most 40
     // elements per thread (registers) and a 96 KiB LDS buffer
-    long long w = image_cols ? (long long)a.cb * std::max(1, c->fft_pix) : c->fft_cols;
+    // (only the coil-sum epilogue needs all coils of a pixel in one panel; an
+    // image prologue alone works per column, and with c->fft_pro_cols > 0
+    // takes panels of that many columns)
+    const bool whole_pix = a.epilogue == EPI_IMAGE || (image_cols && c->fft_pro_cols <= 0);
+    long long w = whole_pix ? (long long)a.cb * std::max(1, c->fft_pix)
+                            : (image_cols ? c->fft_pro_cols : c->fft_cols);
     if (w > a.inner) w = a.inner;
     auto fits = [&](int tc) {
       return tc > 0 && (long long)L * tc <= 40LL * 256 &&
              sizeof(float2) * ((size_t)L * tc + L) <= 96 * 1024;
     };
     int TC = pass_tc_for((int)w);
-    while (!fits(TC) && w > (image_cols ? a.cb : 1)) {
-      w = image_cols ? std::max<long long>(a.cb, w - a.cb) : std::max<long long>(1, w / 2);
+    while (!fits(TC) && w > (whole_pix ? a.cb : 1)) {
+      w = whole_pix ? std::max<long long>(a.cb, w - a.cb) : std::max<long long>(1, w / 2);
       TC = pass_tc_for((int)w);
     }
     if (fits(TC)) {
@@ -610,6 +648,10 @@ int launch_pass(cs_ctx* c, PassArgs& a, long long n_outer) {
       a.vec_out = c->fft_vec && even && a.epilogue != EPI_IMAGE && a.dst_ldc == a.cb &&
                   a.dst_c0 == 0 && a.dst_os % 2 == 0 && a.dst_rs % 2 == 0 &&
                   ((uintptr_t)a.dst & 15) == 0;
+      // image prologue on coil pairs of one pixel (even cb and map offsets)
+      a.vec_img = c->fft_vec_img && even && a.prologue == PRO_IMAGE && !a.premask &&
+                  a.cb % 2 == 0 && a.maps_ldc % 2 == 0 && a.maps_c0 % 2 == 0 &&
+                  ((uintptr_t)a.maps & 15) == 0;
       const long long nblk = (a.inner + a.Wt - 1) / a.Wt;
       a.nblk = nblk;
       if (nblk * n_outer > 0x7fffffffLL || n_outer < 1)

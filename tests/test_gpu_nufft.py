@@ -137,10 +137,11 @@ def test_interp_variants_agree(kind, C):
 def test_paired_accesses_are_bit_identical(kind, C, monkeypatch):
     """The 16-byte coil-pair accesses of the grid FFT passes, the
     interpolation and the merge (the default) against one coil per access
-    (CS_FFT_VEC=0 and CS_GRID_VEC=0 when the context is made): the same
-    values move in the same order, so the forward, adjoint and normal
-    applies agree bit for bit (odd coil counts take the one-coil path
-    either way)."""
+    (CS_FFT_VEC=0, CS_FFT_VEC_IMG=0 and CS_GRID_VEC=0 when the context is
+    made, with the image-prologue passes in whole-pixel panels,
+    CS_FFT_PRO_COLS=0): the same values move in the same order, so the
+    forward, adjoint and normal applies agree bit for bit (odd coil counts
+    take the one-coil path either way)."""
     dev()
     import torch
     from paper_2305_06482_amd import Context
@@ -160,8 +161,9 @@ def test_paired_accesses_are_bit_identical(kind, C, monkeypatch):
     x = synth.phantom(shape, 2) + 0.1 * rng_c(shape, 11)
     mt, xt = t(maps), t(x)
     outs = []
-    for env in ({}, {"CS_FFT_VEC": "0", "CS_GRID_VEC": "0"}):
-        for k in ("CS_FFT_VEC", "CS_GRID_VEC"):
+    knobs = ("CS_FFT_VEC", "CS_FFT_VEC_IMG", "CS_GRID_VEC", "CS_FFT_PRO_COLS")
+    for env in ({}, {k: "0" for k in knobs}):
+        for k in knobs:
             monkeypatch.delenv(k, raising=False)
         for k, v in env.items():
             monkeypatch.setenv(k, v)
