@@ -477,6 +477,7 @@ int create_impl(const cs_geom* g, void* workspace, size_t ws_bytes, void* stream
   if (const char* e = std::getenv("CS_FFT_VEC")) c->fft_vec = std::atoi(e) != 0;
   if (const char* e = std::getenv("CS_FFT_PRO_COLS")) c->fft_pro_cols = std::atoi(e);
   if (const char* e = std::getenv("CS_FFT_VEC_IMG")) c->fft_vec_img = std::atoi(e) != 0;
+  if (const char* e = std::getenv("CS_FFT_SUM_ROWS")) c->fft_sum_rows = std::atoi(e) != 0;
   if (const char* e = std::getenv("CS_GRID_VEC")) c->grid_vec = std::atoi(e) != 0;
   if (const char* e = std::getenv("CS_FFT_XCD")) c->fft_xcd = std::atoi(e) != 0;
   auto reqs = ws_requests(c);

@@ -61,6 +61,7 @@ struct PassArgs {
   // per thread and row (grid source / destination with contiguous columns)
   int vec_in, vec_out;
   int vec_img;  // the image prologue on coil pairs of one pixel
+  int sum_rows;  // coil-sum epilogue: one thread per (row, pixel)
 };
 
 // Work-groups are dealt to the 8 XCDs in turn (group b to XCD b mod 8), and
@@ -122,6 +123,7 @@ struct cs_ctx {
   int fft_pix = 1, fft_cols = 16;
   int fft_pro_cols = 16;  // > 0: image-prologue passes in panels of this many columns
   int fft_vec_img = 1;    // image prologue loads maps as coil pairs
+  int fft_sum_rows = 1;   // coil-sum epilogue over all threads of a panel
   int fft_vec = 1;  // paired-column loads and stores in the grid passes
   int grid_vec = 1;  // paired-coil accesses in the interpolation and merge
   int fft_xcd = 1;                // XCD-contiguous panel order in the FFT passes

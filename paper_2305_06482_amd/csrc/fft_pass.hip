@@ -31,6 +31,13 @@ __device__ __forceinline__ float2 csub(float2 a, float2 b) {
 __device__ __forceinline__ float2 cscale(float2 a, float s) {
   return make_float2(a.x * s, a.y * s);
 }
+// a s, then + b when add: each product and sum rounded on its own (no fused
+// multiply-add), so that every thread mapping of a pass gives the same bits
+__device__ __forceinline__ float2 cscale_add(float2 a, float s, bool add, float2 b) {
+  float2 r = make_float2(__fmul_rn(a.x, s), __fmul_rn(a.y, s));
+  if (add) r = make_float2(__fadd_rn(r.x, b.x), __fadd_rn(r.y, b.y));
+  return r;
+}
 // multiply by -i (dir < 0) or +i (dir > 0)
 __device__ __forceinline__ float2 mul_i(float2 a, int dir) {
   return dir < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
@@ -475,15 +482,29 @@ __global__ __launch_bounds__(256) void k_pass_t(PassArgs a) {
       }
     }
     __syncthreads();
-    if (colok && c == 0) {
+    if (a.sum_rows) {
+      // the coil sums spread over all threads, one (row, pixel) each, every
+      // pixel's coils still added in order
+      const int npix = ncol / a.cb;
+      const long long p0 = col0 / a.cb;
+      for (int k = tid; k < npix * a.n_out; k += NT) {
+        const int t = k / npix, j = k - t * npix;
+        const long long pp = p0 + j;
+        const float2* rv = buf + (a.pad_out ? wrap_row(t, a.n_out, L) : t) * TC + j * a.cb;
+        float2 acc = make_float2(0.f, 0.f);
+        for (int cc = 0; cc < a.cb; ++cc) acc = cadd(acc, rv[cc]);
+        const long long o = (long long)t * a.P + pp;
+        a.img_out[o] = cscale_add(acc, a.da[t] * a.dp[pp], a.accumulate,
+                                  a.accumulate ? a.img_out[o] : make_float2(0.f, 0.f));
+      }
+    } else if (colok && c == 0) {
       const float dpv = a.dp[p];
       float2 prev[NR];
-      if (a.accumulate) {
 #pragma unroll
-        for (int i = 0; i < NR; ++i) {
-          const int t = tr + i * TR;
-          prev[i] = t < a.n_out ? a.img_out[(long long)t * a.P + p] : make_float2(0.f, 0.f);
-        }
+      for (int i = 0; i < NR; ++i) {
+        const int t = tr + i * TR;
+        prev[i] = a.accumulate && t < a.n_out ? a.img_out[(long long)t * a.P + p]
+                                              : make_float2(0.f, 0.f);
       }
 #pragma unroll
       for (int i = 0; i < NR; ++i) {
@@ -492,9 +513,7 @@ __global__ __launch_bounds__(256) void k_pass_t(PassArgs a) {
           const float2* rv = buf + (a.pad_out ? wrap_row(t, a.n_out, L) : t) * TC + tc;
           float2 acc = make_float2(0.f, 0.f);
           for (int cc = 0; cc < a.cb; ++cc) acc = cadd(acc, rv[cc]);
-          acc = cscale(acc, a.da[t] * dpv);
-          if (a.accumulate) acc = cadd(acc, prev[i]);
-          a.img_out[(long long)t * a.P + p] = acc;
+          a.img_out[(long long)t * a.P + p] = cscale_add(acc, a.da[t] * dpv, a.accumulate, prev[i]);
         }
       }
     }
@@ -648,6 +667,7 @@ int launch_pass(cs_ctx* c, PassArgs& a, long long n_outer) {
       a.vec_out = c->fft_vec && even && a.epilogue != EPI_IMAGE && a.dst_ldc == a.cb &&
                   a.dst_c0 == 0 && a.dst_os % 2 == 0 && a.dst_rs % 2 == 0 &&
                   ((uintptr_t)a.dst & 15) == 0;
+      a.sum_rows = c->fft_sum_rows;
       // image prologue on coil pairs of one pixel (even cb and map offsets)
       a.vec_img = c->fft_vec_img && even && a.prologue == PRO_IMAGE && !a.premask &&
                   a.cb % 2 == 0 && a.maps_ldc % 2 == 0 && a.maps_c0 % 2 == 0 &&

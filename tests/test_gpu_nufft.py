@@ -139,7 +139,8 @@ def test_paired_accesses_are_bit_identical(kind, C, monkeypatch):
     interpolation and the merge (the default) against one coil per access
     (CS_FFT_VEC=0, CS_FFT_VEC_IMG=0 and CS_GRID_VEC=0 when the context is
     made, with the image-prologue passes in whole-pixel panels,
-    CS_FFT_PRO_COLS=0): the same values move in the same order, so the
+    CS_FFT_PRO_COLS=0, and the coil sums by one thread per pixel,
+    CS_FFT_SUM_ROWS=0): the same values move in the same order, so the
     forward, adjoint and normal applies agree bit for bit (odd coil counts
     take the one-coil path either way)."""
     dev()
@@ -161,7 +162,7 @@ def test_paired_accesses_are_bit_identical(kind, C, monkeypatch):
     x = synth.phantom(shape, 2) + 0.1 * rng_c(shape, 11)
     mt, xt = t(maps), t(x)
     outs = []
-    knobs = ("CS_FFT_VEC", "CS_FFT_VEC_IMG", "CS_GRID_VEC", "CS_FFT_PRO_COLS")
+    knobs = ("CS_FFT_VEC", "CS_FFT_VEC_IMG", "CS_GRID_VEC", "CS_FFT_PRO_COLS", "CS_FFT_SUM_ROWS")
     for env in ({}, {k: "0" for k in knobs}):
         for k in knobs:
             monkeypatch.delenv(k, raising=False)
