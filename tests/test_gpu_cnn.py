@@ -130,6 +130,14 @@ def test_garbage_network_falls_back_to_the_plain_method():
                        cnn=bad)
     assert r1.n_warm_rejected == T and r1.n_warm_accepted == 0
     assert torch.equal(r0.x, r1.x)
+    # the objective monitor in learned mode only reads: with a tolerance no
+    # outer step reaches, nothing falls back and x is unchanged
+    r2 = ctx.recon_run(y, mode="learned", lam=p.lam, T=T, K=K, V=p.V, S=p.S, seed=p.seed,
+                       cnn=bad, monitor=True, mon_tol=0.5)
+    assert r2.n_fallbacks == 0 and r2.n_warm_rejected == T
+    assert len(r2.objective) == T and np.all(np.isfinite(r2.objective))
+    assert r2.objective[-1] < r2.objective0
+    assert torch.equal(r0.x, r2.x)
     bad.close()
     ctx.close()
 
