@@ -252,8 +252,10 @@ typedef struct {
   double ms_warm;
   /* monitor (cs_recon_params.monitor): host array of length >= T filled when
    * non-NULL with F(x^{t0+it+1}) of the accepted iterate after outer
-   * iteration it; F(x^{t0}); the outer iterations replaced by the full-coil
-   * step; and the GPU time of the objective evaluations and fallbacks */
+   * iteration it; F of the iterate the outer loop starts from (x^{t0}, or
+   * the classical-sketch initialisation's result when it runs); the outer
+   * iterations replaced by the full-coil step; and the GPU time of the
+   * objective evaluations and fallbacks */
   double* objective;
   double objective0;
   long long n_fallbacks;
