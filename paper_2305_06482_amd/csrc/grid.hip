@@ -972,13 +972,25 @@ __global__ __launch_bounds__(256) void k_spread_merge(
   const int gx = ix * H::TX + v % H::TX, gy = iy * H::TY + (v / H::TX) % H::TY,
             gz = iz * H::TZ + v / (H::TX * H::TY);
   if (gx >= mx || gy >= my || gz >= mz) return;
-  int tx[6], dxs[6], ty[6], dys[6], tz[6], dzs[6];
-  const int nx_ = halo_cover(gx, ix, ntx, H::TX, mx, tx, dxs);
-  const int ny_ = halo_cover(gy, iy, nty, H::TY, my, ty, dys);
-  int nz_ = 1;
-  tz[0] = 0;
-  dzs[0] = 0;
-  if (NDIM == 3) nz_ = halo_cover(gz, iz, ntz, H::TZ, mz, tz, dzs);
+  // each cover as one word: (its share of the tile index) << 11 | (its share
+  // of the offset in the halo'd tile); the shares of the three axes add up
+  // without carries (tile index < 2^21, offset < 2^11)
+  unsigned cx[6], cy[6], cz[6];
+  int nx_, ny_, nz_ = 1;
+  {
+    int t[6], d[6];
+    nx_ = halo_cover(gx, ix, ntx, H::TX, mx, t, d);
+    for (int k = 0; k < nx_; ++k) cx[k] = ((unsigned)t[k] << 11) | (unsigned)d[k];
+    ny_ = halo_cover(gy, iy, nty, H::TY, my, t, d);
+    for (int k = 0; k < ny_; ++k)
+      cy[k] = ((unsigned)(t[k] * ntx) << 11) | (unsigned)(d[k] * H::EX);
+    cz[0] = 0;
+    if (NDIM == 3) {
+      nz_ = halo_cover(gz, iz, ntz, H::TZ, mz, t, d);
+      for (int k = 0; k < nz_; ++k)
+        cz[k] = ((unsigned)(t[k] * ntx * nty) << 11) | (unsigned)(d[k] * H::EX * H::EY);
+    }
+  }
   float2 acc[NGMAX * CG];
 #pragma unroll
   for (int c = 0; c < NGMAX * CG; ++c) acc[c] = make_float2(0.f, 0.f);
@@ -986,8 +998,8 @@ __global__ __launch_bounds__(256) void k_spread_merge(
   for (int a = 0; a < nz_; ++a)
     for (int b = 0; b < ny_; ++b)
       for (int d = 0; d < nx_; ++d) {
-        const int t = (tz[a] * nty + ty[b]) * ntx + tx[d];
-        const int e = (dzs[a] * H::EY + dys[b]) * H::EX + dxs[d];
+        const unsigned w = cz[a] + cy[b] + cx[d];
+        const int t = (int)(w >> 11), e = (int)(w & 2047u);
         const int s1 = item_off[t + 1];
         for (int sl = item_off[t]; sl < s1; ++sl) {
           const float2* p = P + (size_t)sl * ng * gstride + (size_t)e * CG;
@@ -1074,6 +1086,9 @@ int merge_launch(cs_ctx* c, int cb, float2* grid) {
   if (blocks > 0x7fffffffLL) return fail(c, CS_EINVAL, "spread merge grid too large");
   constexpr int NA = ((kCoilChunk + CG - 1) / CG) * CG;
   const int vec = c->grid_vec && cb % 2 == 0 && NA % 2 == 0 && ((uintptr_t)grid & 15) == 0;
+  // the merge packs a cover's tile index and tile offset into one word
+  if (c->ntiles >= (1LL << 21) || H::EXT >= 2048)
+    return fail(c, CS_EINVAL, "spread merge: too many tiles");
   CS_KLAUNCH(c, K_MERGE, (k_spread_merge<NDIM, CG>), dim3((unsigned)blocks), dim3(256), 0,
              c->stream, c->partial, c->item_off, cb, ng, c->ntile[2], c->ntile[1],
              c->ntile[0], c->mx, c->my, c->mz, grid, c->merge_xcd, vec);
